@@ -1,0 +1,620 @@
+/*
+ * smdl_oracle.c -- plain, slow FP64 CPU reference for split-and-merge dictionary learning.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Used by the tests, the smoke check and the CPU
+ * baseline leg of the benchmark; the product library never links or calls it.
+ * It shares no code, header, table or helper with the HIP path.
+ *
+ * Paper: S. Mukherjee, C. S. Seelamantula, "A split-and-merge dictionary learning
+ * algorithm for sparse representation" (arXiv 1403.4781).
+ *
+ * Layout: every matrix with r rows is column-major (column j starts at A + j*r).
+ * Y is m x N (signal n is column n), D is m x K (atom k is column k).  Sparse codes
+ * are "ELL": for signal n, idx[n*s_max + i] / coef[n*s_max + i], i < nnz[n], in the
+ * order the atoms were selected; unused slots hold idx = -1, coef = 0.
+ *
+ * Functions
+ *   ora_omp         OMP (Section 1 and Appendix B): sparsity- or error-constrained
+ *   ora_mod_update  MOD dictionary update (Section 1): least squares D = Y X^T (X X^T)^-1
+ *   ora_learn       the standard alternation of the two (Section 1; Section 3.1)
+ *   ora_split_merge Algorithm 1 (Section 2)
+ *   ora_mlp_*       the learned support proposer: forward, BCE loss and gradients, Adam
+ *   ora_propose_code  proposer-restricted OMP with full-OMP fallback
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORA_OK 0
+#define ORA_E_ARG (-1)
+#define ORA_E_NUMERIC (-6)
+
+/* ------------------------------------------------------------------------------------ */
+/* small dense helpers                                                                   */
+/* ------------------------------------------------------------------------------------ */
+
+static double dotd(const double* a, const double* b, int n) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/*
+ * Least squares min_z ||b - A z||_2 for A (m x k, column-major, k <= m) by Householder QR.
+ * Writes z (k) and the residual res = b - A z (m), recomputed explicitly from A and z.
+ * work must hold m*k + m doubles.
+ */
+static void lsq_qr(const double* A, int m, int k, const double* b, double* z, double* res, double* work) {
+    double* W = work;          /* m x k copy, overwritten by R and the reflectors */
+    double* c = work + (size_t)m * k;   /* transformed right-hand side */
+    memcpy(W, A, sizeof(double) * (size_t)m * k);
+    memcpy(c, b, sizeof(double) * (size_t)m);
+    for (int j = 0; j < k; ++j) {
+        double* col = W + (size_t)j * m;
+        double norm = 0.0;
+        for (int i = j; i < m; ++i) norm += col[i] * col[i];
+        norm = sqrt(norm);
+        if (norm == 0.0) continue;
+        double alpha = col[j] > 0 ? -norm : norm;   /* reflect onto -sign(x_j) ||x|| e_j */
+        /* v = x - alpha e_j, stored in col[j..m) */
+        col[j] -= alpha;
+        double vnorm2 = 0.0;
+        for (int i = j; i < m; ++i) vnorm2 += col[i] * col[i];
+        if (vnorm2 > 0.0) {
+            /* apply H = I - 2 v v^T / (v^T v) to remaining columns and to c */
+            for (int jj = j + 1; jj < k; ++jj) {
+                double* cj = W + (size_t)jj * m;
+                double t = 0.0;
+                for (int i = j; i < m; ++i) t += col[i] * cj[i];
+                t = 2.0 * t / vnorm2;
+                for (int i = j; i < m; ++i) cj[i] -= t * col[i];
+            }
+            double t = 0.0;
+            for (int i = j; i < m; ++i) t += col[i] * c[i];
+            t = 2.0 * t / vnorm2;
+            for (int i = j; i < m; ++i) c[i] -= t * col[i];
+        }
+        /* R(j,j) = alpha; keep R's upper part in W rows < j+1 of later columns */
+        col[j] = alpha;   /* the reflector is no longer needed for later columns */
+        for (int i = j + 1; i < m; ++i) col[i] = 0.0;
+    }
+    /* back substitution R z = c[0..k) */
+    for (int j = k - 1; j >= 0; --j) {
+        double s = c[j];
+        for (int jj = j + 1; jj < k; ++jj) s -= W[(size_t)jj * m + j] * z[jj];
+        double r = W[(size_t)j * m + j];
+        z[j] = (r != 0.0) ? s / r : 0.0;
+    }
+    for (int i = 0; i < m; ++i) {
+        double s = b[i];
+        for (int j = 0; j < k; ++j) s -= A[(size_t)j * m + i] * z[j];
+        res[i] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* OMP                                                                                   */
+/* ------------------------------------------------------------------------------------ */
+
+/*
+ * Orthogonal matching pursuit of one signal (Section 1 names OMP as the sparse coder;
+ * Section 3.2.2 states its error-constrained form; Definition 1 is the contract met by
+ * the output: ||x||_0 <= s, ||y - D x||_2 <= eps).
+ *
+ * Each step, in this order:
+ *   1. stop if eps > 0 and ||r||_2 <= eps            (error-constrained form)
+ *   2. stop if |I| == s_max                           (sparsity-constrained form)
+ *   3. c = D^T r over the atoms not yet chosen; j = argmax |c_k|, lowest k on exact ties
+ *   4. stop if |c_j| <= tau * ||y||_2                  (nothing left to explain)
+ *   5. stop if ||d_j - P_I d_j||^2 <= dep_tol * ||d_j||^2 (d_j numerically in span D_I)
+ *   6. I <- I + {j}; x_I = argmin ||y - D_I z|| (Householder QR); r = y - D_I x_I
+ *
+ * Trace (optional, per step k < s_max, NaN when the step was not reached):
+ *   gap[k]  = (|c|_(1) - |c|_(2)) / |c|_(1) over the unchosen atoms (0 if |c|_(1) == 0)
+ *   cmax[k] = |c_j| / ||y||_2
+ *   l2[k]   = ||d_j - P_I d_j||^2 / ||d_j||^2 of the atom considered at step k
+ *   rn[k]   = ||r||_2 before step k (rn has s_max+1 entries per signal; the last is final)
+ */
+static void omp_one(const double* D, int m, int K, const double* y, int s_max, double eps,
+                    double tau, double dep_tol, int32_t* idx, double* coef, int32_t* nnz,
+                    double* res_norm, double* gap, double* cmax, double* l2, double* rn,
+                    double* work) {
+    double* r = work;                       /* m      */
+    double* c = r + m;                      /* K      */
+    double* DI = c + K;                     /* m*s    */
+    double* z = DI + (size_t)m * s_max;     /* s      */
+    double* rho = z + s_max;                /* m      */
+    double* zz = rho + m;                   /* s      */
+    double* qw = zz + s_max;                /* m*s+m  */
+    char* chosen = (char*)(qw + (size_t)m * s_max + m);   /* K */
+
+    memset(chosen, 0, (size_t)K);
+    for (int i = 0; i < s_max; ++i) { idx[i] = -1; coef[i] = 0.0; }
+    if (gap) for (int i = 0; i < s_max; ++i) { gap[i] = NAN; cmax[i] = NAN; l2[i] = NAN; }
+    if (rn) for (int i = 0; i <= s_max; ++i) rn[i] = NAN;
+
+    memcpy(r, y, sizeof(double) * (size_t)m);
+    const double ynorm = sqrt(dotd(y, y, m));
+    int k = 0;
+    for (;;) {
+        double rnorm = sqrt(dotd(r, r, m));
+        if (rn) rn[k] = rnorm;
+        if (eps > 0.0 && rnorm <= eps) break;
+        if (k == s_max) break;
+        int j = -1;
+        double best = -1.0, second = -1.0;
+        for (int a = 0; a < K; ++a) {
+            if (chosen[a]) continue;
+            c[a] = dotd(D + (size_t)a * m, r, m);
+            double v = fabs(c[a]);
+            if (v > best) { second = best; best = v; j = a; }
+            else if (v > second) second = v;
+        }
+        if (j < 0) break;   /* every atom already chosen */
+        if (gap) {
+            gap[k] = best > 0.0 ? (best - (second < 0 ? 0.0 : second)) / best : 0.0;
+            cmax[k] = ynorm > 0.0 ? best / ynorm : 0.0;
+        }
+        if (best <= tau * ynorm) break;
+        const double* dj = D + (size_t)j * m;
+        double djn2 = dotd(dj, dj, m);
+        double dep;
+        if (k == 0) {
+            dep = 1.0;
+        } else {
+            lsq_qr(DI, m, k, dj, zz, rho, qw);
+            dep = djn2 > 0.0 ? dotd(rho, rho, m) / djn2 : 0.0;
+        }
+        if (gap) l2[k] = dep;
+        if (dep <= dep_tol) break;
+        chosen[j] = 1;
+        idx[k] = j;
+        memcpy(DI + (size_t)k * m, dj, sizeof(double) * (size_t)m);
+        ++k;
+        lsq_qr(DI, m, k, y, z, r, qw);
+    }
+    for (int i = 0; i < k; ++i) coef[i] = z[i];
+    *nnz = k;
+    if (res_norm) *res_norm = sqrt(dotd(r, r, m));
+    if (rn) rn[s_max] = sqrt(dotd(r, r, m));
+}
+
+static size_t omp_work_size(int m, int K, int s_max) {
+    return (size_t)m + K + (size_t)m * s_max + s_max + m + s_max + (size_t)m * s_max + m + (K / 8 + 2);
+}
+
+int ora_omp(const double* D, int m, int K, const double* Y, int64_t N, int s_max, double eps,
+            double tau, double dep_tol, int32_t* idx, double* coef, int32_t* nnz,
+            double* res_norm, double* tr_gap, double* tr_cmax, double* tr_l2, double* tr_rn) {
+    if (!D || !Y || !idx || !coef || !nnz || m < 1 || K < 1 || N < 0 || s_max < 1) return ORA_E_ARG;
+    const size_t ws = omp_work_size(m, K, s_max);
+#pragma omp parallel
+    {
+        double* work = (double*)malloc(sizeof(double) * ws);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t n = 0; n < N; ++n) {
+            omp_one(D, m, K, Y + (size_t)n * m, s_max, eps, tau, dep_tol,
+                    idx + (size_t)n * s_max, coef + (size_t)n * s_max, nnz + n,
+                    res_norm ? res_norm + n : NULL,
+                    tr_gap ? tr_gap + (size_t)n * s_max : NULL,
+                    tr_gap ? tr_cmax + (size_t)n * s_max : NULL,
+                    tr_gap ? tr_l2 + (size_t)n * s_max : NULL,
+                    tr_rn ? tr_rn + (size_t)n * (s_max + 1) : NULL, work);
+        }
+        free(work);
+    }
+    return ORA_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* MOD                                                                                   */
+/* ------------------------------------------------------------------------------------ */
+
+/*
+ * In-place Cholesky A = L L^T of an n x n SPD matrix (column-major, lower part used).
+ * A pivot d_k is rejected when d_k <= piv_tol * A_kk (A_kk the diagonal entry before
+ * elimination).  Returns 0 on success, -1 on a rejected pivot.
+ */
+static int cholesky(double* A, int n, double piv_tol) {
+    for (int k = 0; k < n; ++k) {
+        double akk0 = A[(size_t)k * n + k];
+        double d = akk0;
+        for (int p = 0; p < k; ++p) d -= A[(size_t)p * n + k] * A[(size_t)p * n + k];
+        if (!(d > piv_tol * akk0) || !(d > 0.0)) return -1;
+        d = sqrt(d);
+        A[(size_t)k * n + k] = d;
+        for (int i = k + 1; i < n; ++i) {
+            double s = A[(size_t)k * n + i];
+            for (int p = 0; p < k; ++p) s -= A[(size_t)p * n + i] * A[(size_t)p * n + k];
+            A[(size_t)k * n + i] = s / d;
+        }
+    }
+    return 0;
+}
+
+#define ORA_CHOL_PIV_TOL 1e-12
+#define ORA_RIDGE 1e-10
+
+/*
+ * MOD update (Section 1 names the Method of Optimal Directions; its closed form is the
+ * least-squares minimiser of ||Y - D X||_F over D for fixed X):
+ *   A = X X^T, B = Y X^T (FP64); act = atoms used by at least one signal (A_kk > 0);
+ *   D_act = B_act A_act^{-1} by Cholesky; a rejected pivot triggers one retry with
+ *   A_act + lambda I, lambda = 1e-10 * max diag; unused atoms keep their previous value;
+ *   finally every column with nonzero norm is scaled to unit length.
+ * D is in/out (m x K).  Returns ORA_E_NUMERIC if the retry also fails.
+ */
+int ora_mod_update(const double* Y, int m, int64_t N, const int32_t* idx, const double* coef,
+                   const int32_t* nnz, int s_max, int K, double* D, int32_t* n_unused,
+                   int32_t* ridge_used) {
+    if (!Y || !idx || !coef || !nnz || !D || m < 1 || K < 1 || N < 0 || s_max < 1) return ORA_E_ARG;
+    double* A = (double*)calloc((size_t)K * K, sizeof(double));
+    double* B = (double*)calloc((size_t)m * K, sizeof(double));
+    for (int64_t n = 0; n < N; ++n) {
+        const int32_t* in = idx + (size_t)n * s_max;
+        const double* cn = coef + (size_t)n * s_max;
+        const double* yn = Y + (size_t)n * m;
+        for (int a = 0; a < nnz[n]; ++a) {
+            int ka = in[a];
+            for (int b = 0; b < nnz[n]; ++b) A[(size_t)in[b] * K + ka] += cn[a] * cn[b];
+            for (int i = 0; i < m; ++i) B[(size_t)ka * m + i] += yn[i] * cn[a];
+        }
+    }
+    int* act = (int*)malloc(sizeof(int) * K);
+    int na = 0;
+    for (int k = 0; k < K; ++k) if (A[(size_t)k * K + k] > 0.0) act[na++] = k;
+    if (n_unused) *n_unused = K - na;
+    if (ridge_used) *ridge_used = 0;
+    int status = ORA_OK;
+    if (na > 0) {
+        double* Aa = (double*)malloc(sizeof(double) * (size_t)na * na);
+        double maxd = 0.0;
+        for (int p = 0; p < na; ++p) {
+            for (int q = 0; q < na; ++q) Aa[(size_t)q * na + p] = A[(size_t)act[q] * K + act[p]];
+            if (Aa[(size_t)p * na + p] > maxd) maxd = Aa[(size_t)p * na + p];
+        }
+        double* Acopy = (double*)malloc(sizeof(double) * (size_t)na * na);
+        memcpy(Acopy, Aa, sizeof(double) * (size_t)na * na);
+        if (cholesky(Aa, na, ORA_CHOL_PIV_TOL) != 0) {
+            memcpy(Aa, Acopy, sizeof(double) * (size_t)na * na);
+            for (int p = 0; p < na; ++p) Aa[(size_t)p * na + p] += ORA_RIDGE * maxd;
+            if (ridge_used) *ridge_used = 1;
+            if (cholesky(Aa, na, ORA_CHOL_PIV_TOL) != 0) status = ORA_E_NUMERIC;
+        }
+        if (status == ORA_OK) {
+            /* solve A_act z = b for every row b of B_act (one right-hand side per row of D) */
+            double* z = (double*)malloc(sizeof(double) * na);
+            for (int i = 0; i < m; ++i) {
+                for (int p = 0; p < na; ++p) z[p] = B[(size_t)act[p] * m + i];
+                for (int p = 0; p < na; ++p) {          /* L w = b */
+                    double s = z[p];
+                    for (int q = 0; q < p; ++q) s -= Aa[(size_t)q * na + p] * z[q];
+                    z[p] = s / Aa[(size_t)p * na + p];
+                }
+                for (int p = na - 1; p >= 0; --p) {     /* L^T z = w */
+                    double s = z[p];
+                    for (int q = p + 1; q < na; ++q) s -= Aa[(size_t)p * na + q] * z[q];
+                    z[p] = s / Aa[(size_t)p * na + p];
+                }
+                for (int p = 0; p < na; ++p) D[(size_t)act[p] * m + i] = z[p];
+            }
+            free(z);
+        }
+        free(Aa);
+        free(Acopy);
+    }
+    if (status == ORA_OK) {
+        for (int k = 0; k < K; ++k) {
+            double* d = D + (size_t)k * m;
+            double nrm = sqrt(dotd(d, d, m));
+            if (nrm > 0.0) for (int i = 0; i < m; ++i) d[i] /= nrm;
+        }
+    }
+    free(act);
+    free(A);
+    free(B);
+    return status;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* standard learning and Algorithm 1                                                     */
+/* ------------------------------------------------------------------------------------ */
+
+/* First K columns of Y (m x n), each scaled to unit length (zero columns stay zero):
+   the initialisation rule of Section 3.1 ("first training vectors as the atoms"). */
+static void init_first_columns(const double* Y, int m, int K, double* D) {
+    for (int k = 0; k < K; ++k) {
+        const double* y = Y + (size_t)k * m;
+        double nrm = sqrt(dotd(y, y, m));
+        for (int i = 0; i < m; ++i) D[(size_t)k * m + i] = nrm > 0.0 ? y[i] / nrm : 0.0;
+    }
+}
+
+/*
+ * The standard alternation (Section 1): iters x { X = OMP(D, Y, s); D = MOD(Y, X, D) },
+ * from D = normalised first K columns of Y; then one more OMP so that the returned codes
+ * belong to the returned dictionary (codes skipped when idx is NULL).
+ */
+int ora_learn(const double* Y, int m, int64_t n, int K, int s, int iters, double tau,
+              double dep_tol, double* D, int32_t* idx, double* coef, int32_t* nnz) {
+    if (!Y || !D || n < K || K < 1 || s < 1) return ORA_E_ARG;
+    init_first_columns(Y, m, K, D);
+    int32_t* ix = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * s);
+    double* cf = (double*)malloc(sizeof(double) * (size_t)n * s);
+    int32_t* nz = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int status = ORA_OK;
+    for (int it = 0; it < iters && status == ORA_OK; ++it) {
+        ora_omp(D, m, K, Y, n, s, 0.0, tau, dep_tol, ix, cf, nz, NULL, NULL, NULL, NULL, NULL);
+        status = ora_mod_update(Y, m, n, ix, cf, nz, s, K, D, NULL, NULL);
+    }
+    if (status == ORA_OK && idx)
+        ora_omp(D, m, K, Y, n, s, 0.0, tau, dep_tol, idx, coef, nnz, NULL, NULL, NULL, NULL, NULL);
+    free(ix); free(cf); free(nz);
+    return status;
+}
+
+/*
+ * Algorithm 1 (Section 2).
+ *   Step 1: subset t is the columns perm[offsets[t] .. offsets[t+1]) of Y (the random
+ *           disjoint split is an input).
+ *   Step 2: learn D^(t) (K_t atoms, sparsity s_t) on subset t with ora_learn; X^(t) is
+ *           the final coding of the subset.
+ *   Step 3: Ytilde = [ ||X^(1)||_F D^(1), ..., ||X^(L)||_F D^(L) ] (m x sum K_t); learn D
+ *           (K atoms, sparsity s_merge, iters_merge iterations) on Ytilde, initialised
+ *           with its first K columns.
+ * Then all N signals are coded with D at sparsity s_final (codes in original order).
+ */
+int ora_split_merge(const double* Y, int m, int64_t N, const int64_t* perm, int L,
+                    const int64_t* offsets, const int32_t* K_t, const int32_t* s_t, int K,
+                    int iters_local, int iters_merge, int s_merge, int s_final, double tau,
+                    double dep_tol, double* D_out, int32_t* idx, double* coef, int32_t* nnz,
+                    double* D_local_out, double* scales_out) {
+    if (!Y || !perm || !offsets || !K_t || !s_t || !D_out || L < 1 || offsets[L] != N) return ORA_E_ARG;
+    int64_t sumK = 0;
+    for (int t = 0; t < L; ++t) sumK += K_t[t];
+    if (sumK < K) return ORA_E_ARG;
+    double* Yt = (double*)malloc(sizeof(double) * (size_t)m * sumK);
+    int status = ORA_OK;
+    int64_t col = 0;
+    for (int t = 0; t < L && status == ORA_OK; ++t) {
+        int64_t n = offsets[t + 1] - offsets[t];
+        double* Ys = (double*)malloc(sizeof(double) * (size_t)m * n);
+        for (int64_t i = 0; i < n; ++i)
+            memcpy(Ys + (size_t)i * m, Y + (size_t)perm[offsets[t] + i] * m, sizeof(double) * m);
+        int32_t* ix = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * s_t[t]);
+        double* cf = (double*)malloc(sizeof(double) * (size_t)n * s_t[t]);
+        int32_t* nz = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+        double* Dt = Yt + (size_t)col * m;
+        status = ora_learn(Ys, m, n, K_t[t], s_t[t], iters_local, tau, dep_tol, Dt, ix, cf, nz);
+        if (status == ORA_OK) {
+            double fro2 = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                for (int a = 0; a < nz[i]; ++a) fro2 += cf[(size_t)i * s_t[t] + a] * cf[(size_t)i * s_t[t] + a];
+            double sc = sqrt(fro2);
+            if (D_local_out) memcpy(D_local_out + (size_t)col * m, Dt, sizeof(double) * (size_t)m * K_t[t]);
+            if (scales_out) scales_out[t] = sc;
+            for (int64_t i = 0; i < (int64_t)m * K_t[t]; ++i) Dt[i] *= sc;
+        }
+        col += K_t[t];
+        free(Ys); free(ix); free(cf); free(nz);
+    }
+    if (status == ORA_OK)
+        status = ora_learn(Yt, m, sumK, K, s_merge, iters_merge, tau, dep_tol, D_out, NULL, NULL, NULL);
+    if (status == ORA_OK && idx)
+        ora_omp(D_out, m, K, Y, N, s_final, 0.0, tau, dep_tol, idx, coef, nnz, NULL, NULL, NULL, NULL, NULL);
+    free(Yt);
+    return status;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* learned support proposer                                                              */
+/* ------------------------------------------------------------------------------------ */
+
+/* When zero, ora_bf16 is the identity: the network becomes a smooth FP64 function, which
+   lets the tests pin the backward pass by finite differences. */
+static int g_bf16_enabled = 1;
+void ora_set_bf16(int enabled) { g_bf16_enabled = enabled; }
+
+/* FP64 -> FP32 (round to nearest) -> BF16 (round to nearest even), returned as double. */
+double ora_bf16(double x) {
+    if (!g_bf16_enabled) return x;
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {       /* inf / nan: truncate */
+        u &= 0xffff0000u;
+    } else {
+        uint32_t lsb = (u >> 16) & 1u;
+        u += 0x7fffu + lsb;
+        u &= 0xffff0000u;
+    }
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/*
+ * MLP forward with the rounding points of the GPU path:
+ *   h0 = bf16(y / ||y||_2); z_l = bf16(W_l) h_{l-1} + b_l; h_l = bf16(relu(z_l)) for l < L;
+ *   logits = z_L.  W_l is (out x in) row-major, master values in FP64.
+ * X is B x m (row b = signal b).  acts (optional) receives h_0..h_{L-1} and z_1..z_L
+ * concatenated per sample in layer order for the backward pass.
+ */
+static void mlp_forward_one(int n_layers, const int* widths, const double* const* W,
+                            const double* const* bias, const double* x, double* logits,
+                            double* h_store, double* z_store) {
+    int maxw = 0;
+    for (int l = 0; l <= n_layers; ++l) if (widths[l] > maxw) maxw = widths[l];
+    double* h = (double*)malloc(sizeof(double) * maxw);
+    double* hn = (double*)malloc(sizeof(double) * maxw);
+    double nrm = sqrt(dotd(x, x, widths[0]));
+    for (int i = 0; i < widths[0]; ++i) h[i] = ora_bf16(nrm > 0.0 ? x[i] / nrm : 0.0);
+    size_t hoff = 0, zoff = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        int in = widths[l], out = widths[l + 1];
+        if (h_store) { memcpy(h_store + hoff, h, sizeof(double) * in); hoff += in; }
+        for (int o = 0; o < out; ++o) {
+            double s = bias[l][o];
+            const double* w = W[l] + (size_t)o * in;
+            for (int i = 0; i < in; ++i) s += ora_bf16(w[i]) * h[i];
+            hn[o] = s;
+        }
+        if (z_store) { memcpy(z_store + zoff, hn, sizeof(double) * out); zoff += out; }
+        if (l + 1 < n_layers) {
+            for (int o = 0; o < out; ++o) h[o] = ora_bf16(hn[o] > 0.0 ? hn[o] : 0.0);
+        } else {
+            memcpy(logits, hn, sizeof(double) * out);
+        }
+    }
+    free(h); free(hn);
+}
+
+int ora_mlp_forward(int n_layers, const int* widths, const double* const* W,
+                    const double* const* bias, const double* X, int64_t B, double* logits) {
+    if (n_layers < 1 || !widths || !W || !bias || !X || !logits) return ORA_E_ARG;
+    int K = widths[n_layers];
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < B; ++b)
+        mlp_forward_one(n_layers, widths, W, bias, X + (size_t)b * widths[0], logits + (size_t)b * K, NULL, NULL);
+    return ORA_OK;
+}
+
+/*
+ * Mean binary cross-entropy with logits over all B*K outputs, targets t in {0,1}
+ * (t[b*K + k] = 1 iff atom k is in the OMP support of signal b), and its gradients.
+ * Backward rounding points (same as the GPU): delta_L = (sigmoid(z_L) - t) / (B K);
+ * GEMM operands use bf16(delta_l); dh_{l-1} = bf16(W_l)^T bf16(delta_l);
+ * delta_{l-1} = dh_{l-1} * [z_{l-1} > 0]; dW_l = sum_b bf16(delta_l) h_{l-1}^T;
+ * db_l = sum_b delta_l (unrounded).
+ */
+int ora_mlp_grad(int n_layers, const int* widths, const double* const* W,
+                 const double* const* bias, const double* X, const double* T, int64_t B,
+                 double* loss, double* const* dW, double* const* db) {
+    if (n_layers < 1 || !widths || !W || !bias || !X || !T || !dW || !db) return ORA_E_ARG;
+    int K = widths[n_layers];
+    size_t hsz = 0, zsz = 0;
+    int maxw = 0;
+    for (int l = 0; l < n_layers; ++l) { hsz += widths[l]; zsz += widths[l + 1]; }
+    for (int l = 0; l <= n_layers; ++l) if (widths[l] > maxw) maxw = widths[l];
+    for (int l = 0; l < n_layers; ++l) {
+        memset(dW[l], 0, sizeof(double) * (size_t)widths[l] * widths[l + 1]);
+        memset(db[l], 0, sizeof(double) * (size_t)widths[l + 1]);
+    }
+    double total = 0.0;
+    double* hs = (double*)malloc(sizeof(double) * hsz);
+    double* zs = (double*)malloc(sizeof(double) * zsz);
+    double* logit = (double*)malloc(sizeof(double) * K);
+    double* delta = (double*)malloc(sizeof(double) * maxw);
+    double* dh = (double*)malloc(sizeof(double) * maxw);
+    const double scale = 1.0 / ((double)B * K);
+    for (int64_t b = 0; b < B; ++b) {
+        mlp_forward_one(n_layers, widths, W, bias, X + (size_t)b * widths[0], logit, hs, zs);
+        const double* t = T + (size_t)b * K;
+        for (int k = 0; k < K; ++k) {
+            double z = logit[k];
+            total += (z > 0 ? z : 0.0) - t[k] * z + log1p(exp(-fabs(z)));
+            delta[k] = (1.0 / (1.0 + exp(-z)) - t[k]) * scale;
+        }
+        size_t hoff = hsz, zoff = zsz;
+        for (int l = n_layers - 1; l >= 0; --l) {
+            int in = widths[l], out = widths[l + 1];
+            hoff -= in;
+            zoff -= out;
+            const double* h = hs + hoff;
+            for (int o = 0; o < out; ++o) {
+                db[l][o] += delta[o];
+                double dr = ora_bf16(delta[o]);
+                double* g = dW[l] + (size_t)o * in;
+                for (int i = 0; i < in; ++i) g[i] += dr * h[i];
+            }
+            if (l > 0) {
+                const double* zprev = zs + zoff - in;   /* z_l of the previous layer */
+                for (int i = 0; i < in; ++i) {
+                    double s = 0.0;
+                    for (int o = 0; o < out; ++o) s += ora_bf16(W[l][(size_t)o * in + i]) * ora_bf16(delta[o]);
+                    dh[i] = s;
+                }
+                for (int i = 0; i < in; ++i) delta[i] = zprev[i] > 0.0 ? dh[i] : 0.0;
+            }
+        }
+    }
+    if (loss) *loss = total * scale;
+    free(hs); free(zs); free(logit); free(delta); free(dh);
+    return ORA_OK;
+}
+
+/* One Adam step on a flat parameter vector (bias-corrected, step number t >= 1). */
+void ora_adam(double* w, const double* g, double* mom, double* vel, int64_t n, int t,
+              double lr, double beta1, double beta2, double eps) {
+    double c1 = 1.0 - pow(beta1, t), c2 = 1.0 - pow(beta2, t);
+    for (int64_t i = 0; i < n; ++i) {
+        mom[i] = beta1 * mom[i] + (1.0 - beta1) * g[i];
+        vel[i] = beta2 * vel[i] + (1.0 - beta2) * g[i] * g[i];
+        w[i] -= lr * (mom[i] / c1) / (sqrt(vel[i] / c2) + eps);
+    }
+}
+
+/*
+ * Proposer-restricted OMP with fallback, per signal:
+ *   C = the n_cand atoms with the largest logits (lower atom index first on equal logits),
+ *       visited in increasing atom order;
+ *   x = OMP(D[:, C], y, s_max) mapped back to atom indices;
+ *   if ||y - D x||_2 > eps_fallback: x = OMP(D, y, s_max) and fell_back = 1.
+ * logits: B x K as produced by ora_mlp_forward.
+ */
+int ora_propose_code(const double* D, int m, int K, const double* Y, int64_t N,
+                     const double* logits, int n_cand, int s_max, double eps_fallback,
+                     double tau, double dep_tol, int32_t* idx, double* coef, int32_t* nnz,
+                     uint8_t* fell_back, int32_t* cand_out) {
+    if (!D || !Y || !logits || n_cand < 1 || n_cand > K || s_max < 1) return ORA_E_ARG;
+    const int sm = s_max < n_cand ? s_max : n_cand;
+#pragma omp parallel
+    {
+        int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * n_cand);
+        char* taken = (char*)malloc(K);
+        double* Dc = (double*)malloc(sizeof(double) * (size_t)m * n_cand);
+        double* work = (double*)malloc(sizeof(double) * omp_work_size(m, K, s_max));
+        int32_t* ix = (int32_t*)malloc(sizeof(int32_t) * s_max);
+        double* cf = (double*)malloc(sizeof(double) * s_max);
+        double* r = (double*)malloc(sizeof(double) * m);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t n = 0; n < N; ++n) {
+            const double* lg = logits + (size_t)n * K;
+            memset(taken, 0, K);
+            for (int c = 0; c < n_cand; ++c) {        /* c-th largest, lowest index on ties */
+                int best = -1;
+                for (int k = 0; k < K; ++k)
+                    if (!taken[k] && (best < 0 || lg[k] > lg[best])) best = k;
+                taken[best] = 1;
+            }
+            int nc = 0;
+            for (int k = 0; k < K; ++k) if (taken[k]) cand[nc++] = k;
+            if (cand_out) memcpy(cand_out + (size_t)n * n_cand, cand, sizeof(int32_t) * n_cand);
+            for (int c = 0; c < n_cand; ++c)
+                memcpy(Dc + (size_t)c * m, D + (size_t)cand[c] * m, sizeof(double) * m);
+            const double* y = Y + (size_t)n * m;
+            int32_t nz;
+            for (int i = 0; i < s_max; ++i) { ix[i] = -1; cf[i] = 0.0; }
+            omp_one(Dc, m, n_cand, y, sm, 0.0, tau, dep_tol, ix, cf, &nz, NULL, NULL, NULL, NULL, NULL, work);
+            for (int i = 0; i < m; ++i) r[i] = y[i];
+            for (int a = 0; a < nz; ++a) {
+                ix[a] = cand[ix[a]];
+                for (int i = 0; i < m; ++i) r[i] -= cf[a] * D[(size_t)ix[a] * m + i];
+            }
+            double rnorm = sqrt(dotd(r, r, m));
+            int32_t* on = idx + (size_t)n * s_max;
+            double* oc = coef + (size_t)n * s_max;
+            if (rnorm > eps_fallback) {
+                omp_one(D, m, K, y, s_max, 0.0, tau, dep_tol, on, oc, nnz + n, NULL, NULL, NULL, NULL, NULL, work);
+                if (fell_back) fell_back[n] = 1;
+            } else {
+                for (int i = 0; i < s_max; ++i) { on[i] = ix[i]; oc[i] = cf[i]; }
+                for (int i = nz; i < s_max; ++i) { on[i] = -1; oc[i] = 0.0; }
+                nnz[n] = nz;
+                if (fell_back) fell_back[n] = 0;
+            }
+        }
+        free(cand); free(taken); free(Dc); free(work); free(ix); free(cf); free(r);
+    }
+    return ORA_OK;
+}
