@@ -1,0 +1,202 @@
+"""Benchmark: split-and-merge dictionary learning with plain and learned-proposal OMP on one
+MI355X, at 8x8-patch scale (m=64, K=256, s=8).
+
+One step = one pass of the whole hot path over one synthetic batch, inputs resident in HBM:
+  1. Algorithm 1 on N=100000 signals: 20 subsets of 5000, local K=256, s=8, 20 MOD
+     iterations each (all subsets batched per launch, iterations replayed as a HIP graph);
+     merge of the 5120 pooled atoms to K=256 with s=4 and 20 iterations; final OMP coding of
+     all N signals at s=8;
+  2. labels for the proposer: plain OMP of 200000 fresh training signals with the learned D;
+  3. proposer training (MLP 64-512-512-256, BF16 GEMMs, Adam) for `--epochs` epochs;
+  4. coding of 100000 fresh evaluation signals, plain and with the trained proposer (top 24
+     candidates, full-OMP fallback when ||r|| > 1.1 x the plain RMS residual).
+value = signals sparse-coded at (m=64, K=256, s=8) per second of the whole step (the local
+codings of every iteration, the final coding, the labels and both evaluation codings).
+
+Prints one JSON line (rank 0, single GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+ALGO_FLOPS_NOTE = "2mK + K s(s-1) + 3Ks + 2 sum_k k(k+1) + s(s+1) flops per signal (m=64,K=256,s=8: 53656)"
+
+
+def omp_flops_per_signal(m: int, K: int, s: int) -> int:
+    """Algorithmic FP32 flops of one OMP coding (correlations, greedy updates, Cholesky data,
+    final back-substitution)."""
+    return 2 * m * K + K * s * (s - 1) + 3 * K * s + 2 * sum(k * (k + 1) for k in range(s)) + s * (s + 1)
+
+
+def omp_bytes_per_signal(m: int, s: int) -> int:
+    """Algorithmic HBM bytes of one OMP coding: the signal in, the ELL code out."""
+    return 4 * m + 8 * s + 4
+
+
+def cpu_baseline(w, sample_subsets: int, sample_n: int, iters: int):
+    """The FP64 oracle on a bounded sample of the same workload, timed on the host cores."""
+    import oracle
+    from paper_1403_4781_amd import synth
+    oracle.build()
+    idx = w.perm[: sample_subsets * sample_n]
+    Ys = w.Y[idx]
+    perm = np.arange(len(idx), dtype=np.int64)
+    offs = np.arange(sample_subsets + 1, dtype=np.int64) * sample_n
+    t0 = time.perf_counter()
+    oracle.split_merge(Ys, perm, offs, [256] * sample_subsets, [8] * sample_subsets, 256, iters, iters, 4, 8)
+    dt = time.perf_counter() - t0
+    codings = sample_subsets * sample_n * (iters + 1) + len(idx)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": codings / dt, "unit": "signals sparse-coded/sec (m=64,K=256,s=8)", "cores": threads,
+            "kind": "oracle",
+            "sample": f"Algorithm 1 on {sample_subsets} subsets x {sample_n} signals of the same data, "
+                      f"{iters}+{iters} iterations, final coding of {len(idx)}: {codings} codings in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-subsets", type=int, default=2)
+    ap.add_argument("--cpu-n", type=int, default=5000)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--omp-only", type=int, default=0,
+                    help="only run the final-coding kernel this many times (for profilers)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1403_4781_amd as smdl
+    from paper_1403_4781_amd import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.patch_scale(N=100000, L=20, iters=args.iters)
+    Ytr = synth.fresh_signals(w, synth.STREAM_TRAIN, 200000, 8, 0.02)
+    Yev = synth.fresh_signals(w, synth.STREAM_EVAL, 100000, 8, 0.02)
+    h = smdl.Handle(0)
+    Y = torch.from_numpy(w.Y).to(dev)
+    Yt = torch.from_numpy(Ytr).to(dev)
+    Ye = torch.from_numpy(Yev).to(dev)
+    perm = torch.from_numpy(w.perm).to(dev)
+    widths = [64, 512, 512, 256]
+    Ws, bs = synth.mlp_init(widths)
+    torch.cuda.synchronize()
+
+    if args.omp_only:
+        D = torch.from_numpy(synth.gaussian_dictionary(np.random.default_rng(1), 64, 256).astype(np.float32)).to(dev)
+        for _ in range(args.omp_only):
+            h.omp_code(D, Y, 8)
+        torch.cuda.synchronize()
+        print(json.dumps({"omp_only": args.omp_only, "last_kernel_ms": h.last_kernel_ms()}))
+        return
+
+    def step():
+        info = {}
+        D, X, _, _ = h.split_merge_learn(Y, perm, w.offsets, w.K_local, w.s_local, w.K, w.iters_local,
+                                         w.iters_merge, w.s_merge, w.s_final)
+        info["phase_ms"] = h.phase_ms()
+        info["final_kernel_ms"] = h.last_kernel_ms()
+        labels = h.omp_code(D, Yt, 8)
+        prop = h.proposer(Ws, bs)
+        losses = prop.train(Yt, labels, epochs=args.epochs, batch=1024, lr=1e-3, shuffle_seed=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xp, rn = h.omp_code(D, Ye, 8, res_norm=True)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        info["plain_kernel_ms"] = h.last_kernel_ms()
+        eps_fb = 1.1 * float(torch.sqrt((rn.double() ** 2).mean()).item())
+        t0 = time.perf_counter()
+        Xl, fb, nfb, _ = h.omp_code_proposed(prop, D, Ye, 8, 24, eps_fb)
+        torch.cuda.synchronize()
+        t_learn = time.perf_counter() - t0
+        info.update(t_plain=t_plain, t_learn=t_learn, nfb=nfb, losses=losses, prop_ms=h.prop_phase_ms())
+        info["D"], info["Xp"], info["Xl"] = D, Xp, Xl
+        prop.close()
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+
+    last = infos[-1]
+    D = last["D"]
+    # representation error of both evaluation codings (FP64 on the GPU, plain torch)
+    def rmse(X):
+        Xd = X.dense(256).double()
+        R = Ye.double() - Xd @ D.double()
+        return float(torch.sqrt((R ** 2).mean()).item())
+    r_plain, r_learn = rmse(last["Xp"]), rmse(last["Xl"])
+    n_local = int(w.N * (w.iters_local + 1))
+    codings = n_local + w.N + Ytr.shape[0] + 2 * Yev.shape[0]
+    value = codings / dt
+
+    # roofline of the dominant kernel: the fused OMP kernel, timed on the plain evaluation pass
+    kms = float(np.mean([i["plain_kernel_ms"] for i in infos]))
+    f_sig = omp_flops_per_signal(64, 256, 8)
+    achieved = f_sig * Yev.shape[0] / (kms * 1e-3) / 1e12
+    plain_sps = Yev.shape[0] / (kms * 1e-3)
+    prop_ms = last["prop_ms"]
+    learned_sps = Yev.shape[0] / (sum(prop_ms) * 1e-3)
+    out = {
+        "metric": "signals sparse-coded/sec (m=64,K=256,s=8), learned vs plain, equal RMSE",
+        "value": value,
+        "unit": "signals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (OMP, MOD products f64, solve f64); bf16 proposer GEMMs",
+        "data": "synthetic (Gaussian unit-atom dictionary, s=8 sparse codes, sigma=0.02 noise)",
+        "config": {"workload": "split_merge_m64_K256_s8_N100000 + proposer_64-512-512-256_top24",
+                   "N": w.N, "L": w.L, "n_local": 5000, "K": 256, "s": 8, "iters_local": w.iters_local,
+                   "iters_merge": w.iters_merge, "s_merge": 4, "train_pairs": int(Ytr.shape[0]),
+                   "eval_signals": int(Yev.shape[0]), "epochs": args.epochs, "codings_per_step": codings},
+        "plain_signals_per_s": plain_sps,
+        "learned_signals_per_s": learned_sps,
+        "learned_vs_plain": learned_sps / plain_sps,
+        "rmse_plain": r_plain,
+        "rmse_learned": r_learn,
+        "rmse_ratio": r_learn / r_plain,
+        "fallback_rate": last["nfb"] / Yev.shape[0],
+        "phase_ms": {"local": last["phase_ms"][0], "merge": last["phase_ms"][1],
+                     "final": last["phase_ms"][2], "final_kernel": last["final_kernel_ms"],
+                     "plain_eval_kernel": kms, "proposer_net_topk": prop_ms[0],
+                     "proposer_restricted": prop_ms[1], "proposer_fallback": prop_ms[2]},
+        "train_loss": last["losses"][-1] if last["losses"] else None,
+        "roofline": {"kernel": "omp_fused (plain OMP pass, N=100000)", "bound": "alu",
+                     "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s", "frac": achieved / 157.3,
+                     "traffic": None, "per_signal_flops": f_sig,
+                     "per_signal_bytes": omp_bytes_per_signal(64, 8)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_subsets, args.cpu_n, args.cpu_iters)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

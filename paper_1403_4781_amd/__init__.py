@@ -1,0 +1,366 @@
+"""Split-and-merge dictionary learning on MI355X (gfx950): Python binding of libsmdl.
+
+Thin ctypes layer over the C ABI declared in ``include/smdl.h``: it checks tensor
+shapes/devices, marshals pointers and sizes, and returns torch tensors.  Every step of
+the computation runs in the library's HIP kernels; there is no fallback.  The library is
+loaded on first use (``lib()``, or creating a :class:`Handle`), which raises if
+``libsmdl.so`` is missing.
+
+Conventions: signals ``Y`` are a CUDA float32 tensor of shape (N, m) (row n = signal n,
+i.e. the column-major m x N matrix of the paper's problem statement), a dictionary ``D``
+has shape (K, m) (row k = atom k).  Sparse codes are :class:`Codes` (ELL layout).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+__all__ = ["Handle", "Codes", "Proposer", "SmdlError", "LIB_PATH", "lib"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsmdl.so")
+
+SMDL_PER_SUBSET_LAUNCH = 1
+SMDL_NO_GRAPH = 2
+
+_STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_UNSUPPORTED", -4: "E_NOMEM", -5: "E_HIP",
+           -6: "E_NUMERIC", -7: "E_STATE"}
+
+
+class SmdlError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"smdl {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Codes(C.Structure):
+    _fields_ = [("idx", C.c_void_p), ("coef", C.c_void_p), ("nnz", C.c_void_p), ("s_max", C.c_int32)]
+
+
+class _Subsets(C.Structure):
+    _fields_ = [("L", C.c_int), ("perm", C.c_void_p), ("offsets", C.POINTER(C.c_int64)),
+                ("K_local", C.POINTER(C.c_int32)), ("s_local", C.POINTER(C.c_int32))]
+
+
+class _LearnOpts(C.Structure):
+    _fields_ = [("iters_local", C.c_int), ("iters_merge", C.c_int), ("s_merge", C.c_int),
+                ("s_final", C.c_int), ("flags", C.c_uint32)]
+
+
+class _TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("adam_eps", C.c_float), ("shuffle_seed", C.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1403_4781_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = C.c_void_p, C.c_int, C.c_int64, C.c_float
+    sigs = {
+        "smdl_create": [C.POINTER(vp), i32, vp],
+        "smdl_destroy": [vp],
+        "smdl_last_error": [vp],
+        "smdl_version": [],
+        "smdl_gram": [vp, vp, i32, i32, vp],
+        "smdl_omp_code": [vp, vp, i32, i32, vp, i64, i32, f32, _Codes, vp],
+        "smdl_mod_update": [vp, vp, i32, i64, _Codes, i32, vp, C.POINTER(C.c_int32)],
+        "smdl_learn": [vp, vp, i32, i64, i32, i32, i32, vp, _Codes],
+        "smdl_split_merge_learn": [vp, vp, i32, i64, C.POINTER(_Subsets), i32, C.POINTER(_LearnOpts), vp,
+                                   _Codes, vp, C.POINTER(C.c_double)],
+        "smdl_prop_create": [vp, i32, C.POINTER(C.c_int), C.POINTER(C.POINTER(C.c_float)),
+                             C.POINTER(C.POINTER(C.c_float)), C.POINTER(vp)],
+        "smdl_prop_destroy": [vp],
+        "smdl_prop_get": [vp, vp, C.POINTER(C.POINTER(C.c_float)), C.POINTER(C.POINTER(C.c_float))],
+        "smdl_prop_logits": [vp, vp, vp, i64, vp],
+        "smdl_prop_grad": [vp, vp, vp, i64, _Codes, C.POINTER(C.c_float), C.POINTER(vp), C.POINTER(vp)],
+        "smdl_prop_train": [vp, vp, vp, i64, _Codes, C.POINTER(_TrainOpts), C.POINTER(C.c_float)],
+        "smdl_omp_code_proposed": [vp, vp, vp, i32, i32, vp, i64, i32, i32, f32, _Codes, vp,
+                                   C.POINTER(C.c_int64), vp],
+        "smdl_prop_phase_ms": [vp, C.POINTER(C.c_float)],
+        "smdl_tune": [vp, vp, i32, i32, vp, i64, i32],
+        "smdl_get_tile": [vp, i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+        "smdl_set_tile": [vp, i32, i32, i32, i32],
+        "smdl_set_autotune": [vp, i32],
+        "smdl_phase_ms": [vp, C.POINTER(C.c_float)],
+        "smdl_last_kernel_ms": [vp, C.POINTER(C.c_float)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.smdl_last_error.restype = C.c_char_p
+    L.smdl_destroy.restype = None
+    return L
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded libsmdl (ctypes.CDLL); raises ImportError if it is not built."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dev_tensor(t, dtype, name, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+@dataclass
+class Codes:
+    """ELL sparse codes: idx (N, s) int32, coef (N, s) float32, nnz (N,) int32 (device)."""
+    idx: torch.Tensor
+    coef: torch.Tensor
+    nnz: torch.Tensor
+
+    @staticmethod
+    def empty(N: int, s: int, device) -> "Codes":
+        return Codes(torch.empty((N, s), dtype=torch.int32, device=device),
+                     torch.empty((N, s), dtype=torch.float32, device=device),
+                     torch.empty((N,), dtype=torch.int32, device=device))
+
+    @property
+    def s_max(self) -> int:
+        return self.idx.shape[1]
+
+    def _c(self) -> _Codes:
+        return _Codes(self.idx.data_ptr(), self.coef.data_ptr(), self.nnz.data_ptr(), self.s_max)
+
+    def dense(self, K: int) -> torch.Tensor:
+        """Dense (N, K) code matrix (row n = x_n)."""
+        N, s = self.idx.shape
+        X = torch.zeros((N, K), dtype=torch.float32, device=self.idx.device)
+        ok = torch.arange(s, device=self.idx.device)[None, :] < self.nnz[:, None]
+        rows = torch.arange(N, device=self.idx.device)[:, None].expand(N, s)
+        X[rows[ok], self.idx[ok].long()] = self.coef[ok]
+        return X
+
+
+class Handle:
+    """A library handle bound to one GPU (its own HIP stream)."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p(0)
+        self.device = torch.device("cuda", device)
+        L = lib()
+        torch.cuda.init()
+        st = L.smdl_create(C.byref(self._h), device, None)
+        if st != 0:
+            raise SmdlError(st, "smdl_create failed")
+
+    def close(self):
+        if self._h:
+            lib().smdl_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != 0:
+            raise SmdlError(st, lib().smdl_last_error(self._h).decode())
+
+    # ---- coding ---------------------------------------------------------------------
+    def gram(self, D: torch.Tensor) -> torch.Tensor:
+        K, m = D.shape
+        _dev_tensor(D, torch.float32, "D")
+        G = torch.empty((K, K), dtype=torch.float32, device=D.device)
+        self._check(lib().smdl_gram(self._h, _ptr(D), m, K, _ptr(G)))
+        return G
+
+    def omp_code(self, D: torch.Tensor, Y: torch.Tensor, s_max: int, eps: float = 0.0,
+                 out: Codes | None = None, res_norm: bool = False):
+        K, m = D.shape
+        _dev_tensor(D, torch.float32, "D")
+        _dev_tensor(Y, torch.float32, "Y")
+        if Y.dim() != 2 or Y.shape[1] != m:
+            raise ValueError("Y must have shape (N, m)")
+        N = Y.shape[0]
+        X = out if out is not None else Codes.empty(N, s_max, Y.device)
+        r = torch.empty((N,), dtype=torch.float32, device=Y.device) if res_norm else None
+        self._check(lib().smdl_omp_code(self._h, _ptr(D), m, K, _ptr(Y), N, s_max, float(eps), X._c(), _ptr(r)))
+        return (X, r) if res_norm else X
+
+    def last_kernel_ms(self) -> float:
+        v = C.c_float(0)
+        self._check(lib().smdl_last_kernel_ms(self._h, C.byref(v)))
+        return v.value
+
+    # ---- dictionary update ------------------------------------------------------------
+    def mod_update(self, Y: torch.Tensor, X: Codes, D: torch.Tensor) -> int:
+        """MOD update of D in place; returns the number of unused atoms."""
+        K, m = D.shape
+        _dev_tensor(D, torch.float32, "D")
+        _dev_tensor(Y, torch.float32, "Y")
+        N = Y.shape[0]
+        nu = C.c_int32(0)
+        self._check(lib().smdl_mod_update(self._h, _ptr(Y), m, N, X._c(), K, _ptr(D), C.byref(nu)))
+        return nu.value
+
+    # ---- learning -------------------------------------------------------------------
+    def learn(self, Y: torch.Tensor, K: int, s: int, iters: int, codes: bool = True):
+        _dev_tensor(Y, torch.float32, "Y")
+        N, m = Y.shape
+        D = torch.empty((K, m), dtype=torch.float32, device=Y.device)
+        X = Codes.empty(N, s, Y.device) if codes else None
+        xc = X._c() if X is not None else _Codes(None, None, None, s)
+        self._check(lib().smdl_learn(self._h, _ptr(Y), m, N, K, s, iters, _ptr(D), xc))
+        return D, X
+
+    def split_merge_learn(self, Y: torch.Tensor, perm: torch.Tensor | None, offsets, K_local, s_local,
+                          K: int, iters_local: int, iters_merge: int, s_merge: int, s_final: int,
+                          flags: int = 0, codes: bool = True, local: bool = False):
+        """Algorithm 1.  Returns (D, codes or None, D_local or None, scales (np.float64[L]))."""
+        _dev_tensor(Y, torch.float32, "Y")
+        N, m = Y.shape
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        K_local = np.ascontiguousarray(K_local, dtype=np.int32)
+        s_local = np.ascontiguousarray(s_local, dtype=np.int32)
+        L = len(K_local)
+        if perm is not None:
+            _dev_tensor(perm, torch.int64, "perm", (N,))
+        sub = _Subsets(L, _ptr(perm).value if perm is not None else None,
+                       offsets.ctypes.data_as(C.POINTER(C.c_int64)),
+                       K_local.ctypes.data_as(C.POINTER(C.c_int32)),
+                       s_local.ctypes.data_as(C.POINTER(C.c_int32)))
+        opts = _LearnOpts(iters_local, iters_merge, s_merge, s_final, flags)
+        D = torch.empty((K, m), dtype=torch.float32, device=Y.device)
+        X = Codes.empty(N, s_final, Y.device) if codes else None
+        xc = X._c() if X is not None else _Codes(None, None, None, s_final)
+        Dl = torch.empty((int(K_local.sum()), m), dtype=torch.float32, device=Y.device) if local else None
+        scales = np.zeros(L, dtype=np.float64)
+        self._check(lib().smdl_split_merge_learn(self._h, _ptr(Y), m, N, C.byref(sub), K, C.byref(opts), _ptr(D),
+                                               xc, _ptr(Dl), scales.ctypes.data_as(C.POINTER(C.c_double))))
+        return D, X, Dl, scales
+
+    def phase_ms(self):
+        v = (C.c_float * 3)()
+        self._check(lib().smdl_phase_ms(self._h, v))
+        return list(v)
+
+    # ---- tuning ---------------------------------------------------------------------
+    def tune(self, D: torch.Tensor, Y: torch.Tensor, s_max: int):
+        K, m = D.shape
+        self._check(lib().smdl_tune(self._h, _ptr(D), m, K, _ptr(Y), Y.shape[0], s_max))
+        return self.get_tile(m, K, s_max)
+
+    def get_tile(self, m: int, K: int, s_max: int):
+        a, b = C.c_int(0), C.c_int(0)
+        self._check(lib().smdl_get_tile(self._h, m, K, s_max, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def set_tile(self, K: int, s_max: int, lanes: int, signals_per_item: int):
+        self._check(lib().smdl_set_tile(self._h, K, s_max, lanes, signals_per_item))
+
+    def set_autotune(self, enabled: bool):
+        self._check(lib().smdl_set_autotune(self._h, 1 if enabled else 0))
+
+    # ---- proposer -------------------------------------------------------------------
+    def proposer(self, Ws, bs) -> "Proposer":
+        return Proposer(self, Ws, bs)
+
+    def omp_code_proposed(self, prop: "Proposer", D: torch.Tensor, Y: torch.Tensor, s_max: int, n_cand: int,
+                          eps_fallback: float, want_cand: bool = False):
+        K, m = D.shape
+        _dev_tensor(D, torch.float32, "D")
+        _dev_tensor(Y, torch.float32, "Y")
+        N = Y.shape[0]
+        X = Codes.empty(N, s_max, Y.device)
+        fb = torch.empty((N,), dtype=torch.uint8, device=Y.device)
+        cand = torch.empty((N, n_cand), dtype=torch.int32, device=Y.device) if want_cand else None
+        nfb = C.c_int64(0)
+        self._check(lib().smdl_omp_code_proposed(self._h, prop._p, _ptr(D), m, K, _ptr(Y), N, s_max, n_cand,
+                                               float(eps_fallback), X._c(), _ptr(fb), C.byref(nfb), _ptr(cand)))
+        return X, fb, nfb.value, cand
+
+    def prop_phase_ms(self):
+        v = (C.c_float * 3)()
+        self._check(lib().smdl_prop_phase_ms(self._h, v))
+        return list(v)
+
+
+class Proposer:
+    """The learned support proposer: an MLP y/||y|| -> one logit per atom (on the GPU)."""
+
+    def __init__(self, h: Handle, Ws, bs):
+        self.h = h
+        self.widths = [int(Ws[0].shape[1])] + [int(W.shape[0]) for W in Ws]
+        self._Ws = [np.ascontiguousarray(W, dtype=np.float32) for W in Ws]
+        self._bs = [np.ascontiguousarray(b, dtype=np.float32) for b in bs]
+        n = len(Ws)
+        wa = (C.c_int * (n + 1))(*self.widths)
+        WP = (C.POINTER(C.c_float) * n)(*[W.ctypes.data_as(C.POINTER(C.c_float)) for W in self._Ws])
+        BP = (C.POINTER(C.c_float) * n)(*[b.ctypes.data_as(C.POINTER(C.c_float)) for b in self._bs])
+        self._p = C.c_void_p(0)
+        h._check(lib().smdl_prop_create(h._h, n, wa, WP, BP, C.byref(self._p)))
+
+    def close(self):
+        if self._p:
+            lib().smdl_prop_destroy(self._p)
+            self._p = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_layers(self):
+        return len(self.widths) - 1
+
+    def weights(self):
+        Ws = [np.empty((o, i), np.float32) for i, o in zip(self.widths[:-1], self.widths[1:])]
+        bs = [np.empty((o,), np.float32) for o in self.widths[1:]]
+        n = self.n_layers
+        WP = (C.POINTER(C.c_float) * n)(*[W.ctypes.data_as(C.POINTER(C.c_float)) for W in Ws])
+        BP = (C.POINTER(C.c_float) * n)(*[b.ctypes.data_as(C.POINTER(C.c_float)) for b in bs])
+        self.h._check(lib().smdl_prop_get(self.h._h, self._p, WP, BP))
+        return Ws, bs
+
+    def logits(self, Y: torch.Tensor) -> torch.Tensor:
+        _dev_tensor(Y, torch.float32, "Y")
+        out = torch.empty((Y.shape[0], self.widths[-1]), dtype=torch.float32, device=Y.device)
+        self.h._check(lib().smdl_prop_logits(self.h._h, self._p, _ptr(Y), Y.shape[0], _ptr(out)))
+        return out
+
+    def grad(self, Y: torch.Tensor, labels: Codes):
+        _dev_tensor(Y, torch.float32, "Y")
+        dW = [torch.empty((o, i), dtype=torch.float32, device=Y.device)
+              for i, o in zip(self.widths[:-1], self.widths[1:])]
+        db = [torch.empty((o,), dtype=torch.float32, device=Y.device) for o in self.widths[1:]]
+        n = self.n_layers
+        GW = (C.c_void_p * n)(*[t.data_ptr() for t in dW])
+        GB = (C.c_void_p * n)(*[t.data_ptr() for t in db])
+        loss = C.c_float(0)
+        self.h._check(lib().smdl_prop_grad(self.h._h, self._p, _ptr(Y), Y.shape[0], labels._c(), C.byref(loss), GW, GB))
+        return loss.value, dW, db
+
+    def train(self, Y: torch.Tensor, labels: Codes, epochs: int = 10, batch: int = 1024, lr: float = 1e-3,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, shuffle_seed: int = 0):
+        _dev_tensor(Y, torch.float32, "Y")
+        opts = _TrainOpts(epochs, batch, lr, beta1, beta2, eps, shuffle_seed)
+        losses = (C.c_float * max(1, epochs))()
+        self.h._check(lib().smdl_prop_train(self.h._h, self._p, _ptr(Y), Y.shape[0], labels._c(), C.byref(opts), losses))
+        return list(losses)[:epochs]

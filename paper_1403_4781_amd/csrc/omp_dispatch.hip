@@ -1,0 +1,54 @@
+// Dispatch from a runtime tile choice to the instantiated fused-OMP kernels.
+#include "omp_kernel.h"
+
+namespace smdl_omp {
+#define SMDL_OMP_TILE(EM, SM, G, TT) \
+    extern template hipError_t launch_one<EM, SM, G, TT>(const OmpArgs&, int, hipStream_t, int);
+#include "omp_table.inc"
+#undef SMDL_OMP_TILE
+}  // namespace smdl_omp
+
+namespace {
+
+struct TileEntry {
+    int EM, SM, G, TT;
+    hipError_t (*fn)(const OmpArgs&, int, hipStream_t, int);
+};
+
+const TileEntry kTiles[] = {
+#define SMDL_OMP_TILE(EM, SM, G, TT) {EM, SM, G, TT, &smdl_omp::launch_one<EM, SM, G, TT>},
+#include "omp_table.inc"
+#undef SMDL_OMP_TILE
+};
+
+// Smallest instantiated (EM, SM) that covers Kpad / lanes entries and s steps.
+const TileEntry* find_tile(OmpTile t, int Kpad, int s) {
+    if (t.lanes != 16 && t.lanes != 32 && t.lanes != 64) return nullptr;
+    if (Kpad % (4 * t.lanes) != 0) return nullptr;
+    const int E = Kpad / t.lanes;
+    const TileEntry* best = nullptr;
+    for (const TileEntry& e : kTiles) {
+        if (e.G != t.lanes || e.TT != t.tt || e.EM < E || e.SM < s) continue;
+        if (!best || e.EM < best->EM || (e.EM == best->EM && e.SM < best->SM)) best = &e;
+    }
+    return best;
+}
+
+}  // namespace
+
+size_t omp_lds_bytes(OmpTile t, int maxKpad) {
+    const int T = 16 * t.tt;
+    return (size_t)T * (maxKpad + 4) * 4 + T * 4;
+}
+
+// A tile is usable when it is instantiated for (Kpad, s) and its alpha0 staging fits in the
+// 160 KB of LDS of a gfx950 workgroup.
+bool omp_tile_supported(OmpTile t, int Kpad, int s) {
+    return find_tile(t, Kpad, s) != nullptr && omp_lds_bytes(t, Kpad) <= SMDL_LDS_BYTES;
+}
+
+hipError_t launch_omp(OmpTile t, int maxKpad, int maxS, const OmpArgs& a, int grid, hipStream_t st) {
+    const TileEntry* e = find_tile(t, maxKpad, maxS);
+    if (!e || omp_lds_bytes(t, maxKpad) > SMDL_LDS_BYTES) return hipErrorInvalidValue;
+    return e->fn(a, grid, st, maxKpad);
+}

@@ -1,0 +1,458 @@
+// C ABI of the learned support proposer: network state, forward, gradients, Adam training and
+// proposer-restricted OMP with the full-OMP fallback.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "mlp_internal.h"
+#include "smdl_api_internal.h"
+
+struct smdl_prop {
+    smdl_t h = nullptr;
+    int n_layers = 0;
+    std::vector<int> widths;
+    std::vector<float*> W, b, mW, vW, mb, vb;   // FP32 masters and Adam moments
+    std::vector<uint16_t*> Wbf, WbfT;           // BF16 copies (out x in) and (in x out)
+    int step = 0;
+    std::vector<void*> allocs;
+
+    template <class T>
+    T* alloc(size_t n) {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        allocs.push_back(p);
+        return static_cast<T*>(p);
+    }
+};
+
+namespace {
+
+inline int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
+
+// Activation buffers for a batch of Bpad rows (h_0 .. h_{L-1} bf16, deltas, logits).
+struct Acts {
+    std::vector<uint16_t*> h;      // h[l]: Bpad x widths[l]
+    float* logits = nullptr;       // Bpad x K
+    std::vector<float*> dF;        // deltas FP32: dF[l]: Bpad x widths[l+1]
+    std::vector<uint16_t*> dB;     // deltas BF16
+    double* loss_part = nullptr;
+    double* loss = nullptr;
+};
+
+smdl_status get_acts(smdl_t h, smdl_prop_t p, int64_t Bpad, bool train, Acts& a) {
+    const int L = p->n_layers;
+    a.h.resize(L);
+    for (int l = 0; l < L; ++l) {
+        std::string nm = "prop.h" + std::to_string(l);
+        a.h[l] = (uint16_t*)h->ws(nm.c_str(), (size_t)Bpad * p->widths[l] * 2);
+        if (!a.h[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    }
+    a.logits = (float*)h->ws("prop.logits", (size_t)Bpad * p->widths[L] * 4);
+    if (!a.logits) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    if (train) {
+        a.dF.resize(L);
+        a.dB.resize(L);
+        for (int l = 0; l < L; ++l) {
+            std::string nf = "prop.dF" + std::to_string(l), nb = "prop.dB" + std::to_string(l);
+            a.dF[l] = (float*)h->ws(nf.c_str(), (size_t)Bpad * p->widths[l + 1] * 4);
+            a.dB[l] = (uint16_t*)h->ws(nb.c_str(), (size_t)Bpad * p->widths[l + 1] * 2);
+            if (!a.dF[l] || !a.dB[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+        }
+        a.loss_part = (double*)h->ws("prop.lossp", (size_t)Bpad * 8);
+        a.loss = (double*)h->ws("prop.loss", 8);
+        if (!a.loss_part || !a.loss) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    }
+    return SMDL_OK;
+}
+
+// Forward pass over M rows (rows >= B of h_0 are zero).  logits_out: M x K FP32.
+hipError_t enqueue_forward(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, int64_t M,
+                           const int32_t* rows, Acts& a, float* logits_out) {
+    const int L = p->n_layers;
+    const int m = p->widths[0];
+    hipError_t e = launch_prep_input(Y, B, m, m, M, rows, a.h[0], h->stream);
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < L; ++l) {
+        GemmArgs g{};
+        g.A = a.h[l];
+        g.lda = p->widths[l];
+        g.B = p->Wbf[l];
+        g.ldb = p->widths[l];
+        g.M = (int)M;
+        g.N = p->widths[l + 1];
+        g.K = p->widths[l];
+        g.ldc = p->widths[l + 1];
+        g.bias = p->b[l];
+        if (l + 1 < L) {
+            g.relu = 1;
+            g.out_bf16 = a.h[l + 1];
+        } else {
+            g.out_f32 = logits_out;
+        }
+        e = launch_gemm(g, false, false, M >= 4096, h->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Loss and gradients for a batch (rows of Y / labels given by `rows`, or the first B).
+hipError_t enqueue_grad(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, const int32_t* rows,
+                        const smdl_codes& labels, Acts& a, float* const* dW, float* const* db) {
+    const int L = p->n_layers;
+    const int K = p->widths[L];
+    const int64_t Bpad = pad32(B);
+    hipError_t e = enqueue_forward(h, p, Y, B, Bpad, rows, a, a.logits);
+    if (e != hipSuccess) return e;
+    e = launch_bce(a.logits, B, Bpad, K, labels.idx, labels.nnz, labels.s_max, rows, 1.0f / ((float)B * K),
+                   a.dF[L - 1], a.dB[L - 1], a.loss_part, a.loss, h->stream);
+    if (e != hipSuccess) return e;
+    for (int l = L - 1; l >= 0; --l) {
+        // dW_l = delta_l^T h_l   (M = out, N = in, K = Bpad), both operands stored transposed
+        GemmArgs g{};
+        g.A = a.dB[l];
+        g.lda = p->widths[l + 1];
+        g.B = a.h[l];
+        g.ldb = p->widths[l];
+        g.M = p->widths[l + 1];
+        g.N = p->widths[l];
+        g.K = (int)Bpad;
+        g.ldc = p->widths[l];
+        g.out_f32 = dW[l];
+        if ((e = launch_gemm(g, true, true, false, h->stream)) != hipSuccess) return e;
+        if ((e = launch_colsum(a.dF[l], Bpad, p->widths[l + 1], db[l], h->stream)) != hipSuccess) return e;
+        if (l > 0) {
+            // delta_{l-1} = (delta_l W_l) * [h_l > 0]   (M = Bpad, N = in, K = out)
+            GemmArgs q{};
+            q.A = a.dB[l];
+            q.lda = p->widths[l + 1];
+            q.B = p->WbfT[l];
+            q.ldb = p->widths[l + 1];
+            q.M = (int)Bpad;
+            q.N = p->widths[l];
+            q.K = p->widths[l + 1];
+            q.ldc = p->widths[l];
+            q.mask_bf16 = a.h[l];
+            q.ldmask = p->widths[l];
+            q.out_f32 = a.dF[l - 1];
+            q.out_bf16 = a.dB[l - 1];
+            if ((e = launch_gemm(q, false, false, false, h->stream)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+smdl_status check_prop(smdl_t h, smdl_prop_t p) {
+    if (!p || p->h != h) return h->fail(SMDL_E_STATE, "proposer does not belong to this handle");
+    return SMDL_OK;
+}
+
+}  // namespace
+
+extern "C" smdl_status smdl_prop_create(smdl_t h, int n_layers, const int* widths, const float* const* W_init,
+                                        const float* const* b_init, smdl_prop_t* out) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    if (!out || !widths || !W_init || !b_init) return h->fail(SMDL_E_ARG, "null pointer");
+    *out = nullptr;
+    if (n_layers < 1 || n_layers > 4) return h->fail(SMDL_E_SHAPE, "1 to 4 layers");
+    for (int l = 0; l <= n_layers; ++l)
+        if (widths[l] < 32 || widths[l] > 4096 || widths[l] % 32)
+            return h->fail(SMDL_E_SHAPE, "layer widths must be multiples of 32 in [32, 4096]");
+    if (widths[0] > SMDL_MAX_M || widths[n_layers] > SMDL_MAX_K)
+        return h->fail(SMDL_E_SHAPE, "input width must be <= 256 and output width <= 1024");
+    for (int l = 0; l < n_layers; ++l)
+        if (!W_init[l] || !b_init[l]) return h->fail(SMDL_E_ARG, "null initial weights");
+    (void)hipSetDevice(h->device);
+    auto* p = new smdl_prop();
+    p->h = h;
+    p->n_layers = n_layers;
+    p->widths.assign(widths, widths + n_layers + 1);
+    for (int l = 0; l < n_layers; ++l) {
+        const size_t nw = (size_t)widths[l] * widths[l + 1], nb = widths[l + 1];
+        float *W = p->alloc<float>(nw), *b = p->alloc<float>(nb);
+        float *mW = p->alloc<float>(nw), *vW = p->alloc<float>(nw), *mb = p->alloc<float>(nb), *vb = p->alloc<float>(nb);
+        uint16_t *Wbf = p->alloc<uint16_t>(nw), *WbfT = p->alloc<uint16_t>(nw);
+        if (!W || !b || !mW || !vW || !mb || !vb || !Wbf || !WbfT) {
+            smdl_prop_destroy(p);
+            return h->fail(SMDL_E_NOMEM, "proposer allocation failed");
+        }
+        p->W.push_back(W);
+        p->b.push_back(b);
+        p->mW.push_back(mW);
+        p->vW.push_back(vW);
+        p->mb.push_back(mb);
+        p->vb.push_back(vb);
+        p->Wbf.push_back(Wbf);
+        p->WbfT.push_back(WbfT);
+        hipError_t e = hipMemcpyAsync(W, W_init[l], nw * 4, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b, b_init[l], nb * 4, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(mW, 0, nw * 4, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(vW, 0, nw * 4, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(mb, 0, nb * 4, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(vb, 0, nb * 4, h->stream);
+        if (e == hipSuccess) e = launch_to_bf16(W, (int64_t)nw, widths[l], widths[l + 1], Wbf, WbfT, h->stream);
+        if (e != hipSuccess) {
+            smdl_prop_destroy(p);
+            return h->hip(e, "proposer init");
+        }
+    }
+    smdl_status st = h->hip(hipStreamSynchronize(h->stream), "proposer init");
+    if (st != SMDL_OK) {
+        smdl_prop_destroy(p);
+        return st;
+    }
+    *out = p;
+    return SMDL_OK;
+}
+
+extern "C" smdl_status smdl_prop_destroy(smdl_prop_t p) {
+    if (!p) return SMDL_E_ARG;
+    if (p->h) (void)hipStreamSynchronize(p->h->stream);
+    for (void* a : p->allocs) (void)hipFree(a);
+    delete p;
+    return SMDL_OK;
+}
+
+extern "C" smdl_status smdl_prop_get(smdl_t h, smdl_prop_t p, float* const* W_host, float* const* b_host) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    smdl_status st = check_prop(h, p);
+    if (st != SMDL_OK) return st;
+    if (!W_host || !b_host) return h->fail(SMDL_E_ARG, "null pointer");
+    for (int l = 0; l < p->n_layers; ++l) {
+        const size_t nw = (size_t)p->widths[l] * p->widths[l + 1], nb = p->widths[l + 1];
+        if (W_host[l] && (st = h->hip(hipMemcpyAsync(W_host[l], p->W[l], nw * 4, hipMemcpyDeviceToHost, h->stream), "get")) != SMDL_OK)
+            return st;
+        if (b_host[l] && (st = h->hip(hipMemcpyAsync(b_host[l], p->b[l], nb * 4, hipMemcpyDeviceToHost, h->stream), "get")) != SMDL_OK)
+            return st;
+    }
+    return h->hip(hipStreamSynchronize(h->stream), "get");
+}
+
+extern "C" smdl_status smdl_prop_logits(smdl_t h, smdl_prop_t p, const float* Y, int64_t N, float* logits) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    smdl_status st = check_prop(h, p);
+    if (st != SMDL_OK) return st;
+    if (N < 0) return h->fail(SMDL_E_ARG, "N must be >= 0");
+    if (N == 0) return SMDL_OK;
+    if (!Y || !logits) return h->fail(SMDL_E_ARG, "null pointer");
+    if (N > INT32_MAX / 4) return h->fail(SMDL_E_SHAPE, "N too large");
+    (void)hipSetDevice(h->device);
+    Acts a;
+    if ((st = get_acts(h, p, N, false, a)) != SMDL_OK) return st;
+    if ((st = h->hip(enqueue_forward(h, p, Y, N, N, nullptr, a, logits), "forward")) != SMDL_OK) return st;
+    return h->hip(hipStreamSynchronize(h->stream), "forward");
+}
+
+static smdl_status check_labels(smdl_t h, const smdl_codes& labels, int64_t N) {
+    if (N > 0 && (!labels.idx || !labels.nnz)) return h->fail(SMDL_E_ARG, "null label arrays");
+    if (labels.s_max < 1 || labels.s_max > SMDL_MAX_S) return h->fail(SMDL_E_SHAPE, "labels.s_max must be in [1, 16]");
+    return SMDL_OK;
+}
+
+extern "C" smdl_status smdl_prop_grad(smdl_t h, smdl_prop_t p, const float* Y, int64_t N, smdl_codes labels,
+                                      float* loss, float* const* dW, float* const* db) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    smdl_status st = check_prop(h, p);
+    if (st != SMDL_OK) return st;
+    if (N < 1) return h->fail(SMDL_E_ARG, "N must be >= 1");
+    if (N > INT32_MAX / 8) return h->fail(SMDL_E_SHAPE, "N too large");
+    if (!Y || !dW || !db) return h->fail(SMDL_E_ARG, "null pointer");
+    if ((st = check_labels(h, labels, N)) != SMDL_OK) return st;
+    for (int l = 0; l < p->n_layers; ++l)
+        if (!dW[l] || !db[l]) return h->fail(SMDL_E_ARG, "null gradient array");
+    (void)hipSetDevice(h->device);
+    Acts a;
+    if ((st = get_acts(h, p, pad32(N), true, a)) != SMDL_OK) return st;
+    if ((st = h->hip(enqueue_grad(h, p, Y, N, nullptr, labels, a, dW, db), "grad")) != SMDL_OK) return st;
+    double l = 0.0;
+    if ((st = h->hip(hipMemcpyAsync(&l, a.loss, 8, hipMemcpyDeviceToHost, h->stream), "loss")) != SMDL_OK) return st;
+    if ((st = h->hip(hipStreamSynchronize(h->stream), "grad")) != SMDL_OK) return st;
+    if (loss) *loss = (float)(l / ((double)N * p->widths[p->n_layers]));
+    return SMDL_OK;
+}
+
+extern "C" smdl_status smdl_prop_train(smdl_t h, smdl_prop_t p, const float* Y, int64_t N, smdl_codes labels,
+                                       const smdl_train_opts* o, float* loss_per_epoch) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    smdl_status st = check_prop(h, p);
+    if (st != SMDL_OK) return st;
+    if (!o || !Y) return h->fail(SMDL_E_ARG, "null pointer");
+    if (o->epochs < 0 || o->batch < 16 || o->batch > 65536) return h->fail(SMDL_E_ARG, "bad epochs or batch size");
+    if (!(o->lr > 0.f) || !(o->beta1 >= 0.f && o->beta1 < 1.f) || !(o->beta2 >= 0.f && o->beta2 < 1.f) || !(o->adam_eps > 0.f))
+        return h->fail(SMDL_E_ARG, "bad Adam parameters");
+    if ((st = check_labels(h, labels, N)) != SMDL_OK) return st;
+    if (N > INT32_MAX / 8) return h->fail(SMDL_E_SHAPE, "N too large");
+    (void)hipSetDevice(h->device);
+    const int L = p->n_layers;
+    const int64_t B = o->batch;
+    const int64_t nb = N / B;
+    Acts a;
+    if ((st = get_acts(h, p, pad32(B), true, a)) != SMDL_OK) return st;
+    std::vector<float*> gW(L), gb(L);
+    for (int l = 0; l < L; ++l) {
+        std::string n1 = "prop.gW" + std::to_string(l), n2 = "prop.gb" + std::to_string(l);
+        gW[l] = (float*)h->ws(n1.c_str(), (size_t)p->widths[l] * p->widths[l + 1] * 4);
+        gb[l] = (float*)h->ws(n2.c_str(), (size_t)p->widths[l + 1] * 4);
+        if (!gW[l] || !gb[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    }
+    int32_t* rows = (int32_t*)h->ws("prop.rows", (size_t)std::max<int64_t>(N, 1) * 4);
+    double* eloss = (double*)h->ws("prop.eloss", 8 * (size_t)std::max(1, nb > 0 ? (int)nb : 1));
+    if (!rows || !eloss) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    std::vector<int32_t> order(N);
+    std::iota(order.begin(), order.end(), 0);
+    uint64_t rng = o->shuffle_seed;
+    auto next = [&rng]() {   // splitmix64
+        uint64_t z = (rng += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    const int K = p->widths[L];
+    for (int ep = 0; ep < o->epochs; ++ep) {
+        if (o->shuffle_seed) {
+            for (int64_t i = N - 1; i > 0; --i) std::swap(order[i], order[next() % (uint64_t)(i + 1)]);
+        }
+        if ((st = h->hip(hipMemcpyAsync(rows, order.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream), "rows")) != SMDL_OK)
+            return st;
+        for (int64_t bi = 0; bi < nb; ++bi) {
+            hipError_t e = enqueue_grad(h, p, Y, B, rows + bi * B, labels, a, gW.data(), gb.data());
+            if (e != hipSuccess) return h->hip(e, "train step");
+            if ((e = hipMemcpyAsync(eloss + bi, a.loss, 8, hipMemcpyDeviceToDevice, h->stream)) != hipSuccess)
+                return h->hip(e, "loss");
+            ++p->step;
+            for (int l = 0; l < L; ++l) {
+                const int64_t nw = (int64_t)p->widths[l] * p->widths[l + 1];
+                e = launch_adam(p->W[l], gW[l], p->mW[l], p->vW[l], nw, p->widths[l], p->widths[l + 1], o->lr, o->beta1,
+                                o->beta2, o->adam_eps, p->step, p->Wbf[l], p->WbfT[l], h->stream);
+                if (e == hipSuccess)
+                    e = launch_adam(p->b[l], gb[l], p->mb[l], p->vb[l], p->widths[l + 1], p->widths[l + 1], 1, o->lr,
+                                    o->beta1, o->beta2, o->adam_eps, p->step, nullptr, nullptr, h->stream);
+                if (e != hipSuccess) return h->hip(e, "adam");
+            }
+        }
+        if (loss_per_epoch) {
+            std::vector<double> el(std::max<int64_t>(nb, 1));
+            if (nb > 0 && (st = h->hip(hipMemcpyAsync(el.data(), eloss, nb * 8, hipMemcpyDeviceToHost, h->stream), "loss")) != SMDL_OK)
+                return st;
+            if ((st = h->hip(hipStreamSynchronize(h->stream), "train")) != SMDL_OK) return st;
+            double s = 0.0;
+            for (int64_t i = 0; i < nb; ++i) s += el[i] / ((double)B * K);
+            loss_per_epoch[ep] = nb > 0 ? (float)(s / nb) : 0.f;
+        }
+    }
+    return h->hip(hipStreamSynchronize(h->stream), "train");
+}
+
+extern "C" smdl_status smdl_omp_code_proposed(smdl_t h, smdl_prop_t p, const float* D, int m, int K,
+                                              const float* Y, int64_t N, int s_max, int n_cand, float eps_fallback,
+                                              smdl_codes X, uint8_t* fell_back, int64_t* n_fallback,
+                                              int32_t* cand_out) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    smdl_status st = check_prop(h, p);
+    if (st != SMDL_OK) return st;
+    if ((st = check_dims(h, m, K, s_max)) != SMDL_OK) return st;
+    if (p->widths[0] != m || p->widths[p->n_layers] != K) return h->fail(SMDL_E_SHAPE, "network widths do not match (m, K)");
+    if (n_cand < s_max || n_cand > 64 || n_cand > K) return h->fail(SMDL_E_SHAPE, "need s_max <= n_cand <= min(64, K)");
+    if (!(eps_fallback >= 0.f)) return h->fail(SMDL_E_ARG, "eps_fallback must be >= 0 (inf allowed)");
+    if (N < 0) return h->fail(SMDL_E_ARG, "N must be >= 0");
+    if ((st = check_codes(h, X, N, s_max)) != SMDL_OK) return st;
+    if (n_fallback) *n_fallback = 0;
+    if (N == 0) return SMDL_OK;
+    if (!D || !Y) return h->fail(SMDL_E_ARG, "null pointer");
+    if (N > INT32_MAX / 64) return h->fail(SMDL_E_SHAPE, "N too large");
+    (void)hipSetDevice(h->device);
+    Acts a;
+    if ((st = get_acts(h, p, N, false, a)) != SMDL_OK) return st;
+    int32_t* cand = cand_out ? cand_out : (int32_t*)h->ws("prop.cand", (size_t)N * n_cand * 4);
+    int32_t* fb_list = (int32_t*)h->ws("prop.fbl", (size_t)N * 4);
+    int32_t* fb_cnt = (int32_t*)h->ws("prop.fbc", 64);
+    if (!cand || !fb_list || !fb_cnt) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    hipError_t e;
+    (void)hipEventRecord(h->ev_prop[0], h->stream);
+    if ((e = enqueue_forward(h, p, Y, N, N, nullptr, a, a.logits)) != hipSuccess) return h->hip(e, "forward");
+    if ((e = launch_topk(a.logits, N, K, n_cand, cand, h->stream)) != hipSuccess) return h->hip(e, "topk");
+    (void)hipEventRecord(h->ev_prop[1], h->stream);
+    // dictionary fragments and Gram for the restricted kernel and the fallback
+    std::vector<SetSpec> sets(1);
+    sets[0].D = D;
+    sets[0].K = K;
+    sets[0].s = s_max;
+    sets[0].Y = Y;
+    sets[0].n = N;
+    sets[0].out0 = 0;
+    CodePlan plan;
+    if ((st = prepare_sets(h, m, sets, "prop", plan)) != SMDL_OK) return st;
+    if ((e = launch_pack_dict_m(plan.pack_desc, 1, plan.maxKpad, m, plan.mchunks, h->stream)) != hipSuccess)
+        return h->hip(e, "pack");
+    if ((e = launch_gram_batched(plan.gram_desc, 1, plan.maxKpad, plan.mchunks, h->stream)) != hipSuccess)
+        return h->hip(e, "gram");
+    if ((e = launch_zero_i32(fb_cnt, 1, h->stream)) != hipSuccess) return h->hip(e, "zero");
+    RestrictedArgs r{};
+    r.D = D;
+    r.gram = sets[0].gram;
+    r.Kpad = sets[0].Kpad;
+    r.m = m;
+    r.K = K;
+    r.Y = Y;
+    r.N = N;
+    r.cand = cand;
+    r.n_cand = n_cand;
+    r.s = std::min(s_max, n_cand);
+    r.eps_fb = std::isinf(eps_fallback) ? INFINITY : eps_fallback;
+    r.tau = SMDL_TAU;
+    r.dep_tol = SMDL_DEP_TOL;
+    r.idx = X.idx;
+    r.coef = X.coef;
+    r.nnz = X.nnz;
+    r.s_out = X.s_max;
+    r.fell_back = fell_back;
+    r.fb_list = fb_list;
+    r.fb_count = fb_cnt;
+    if ((e = launch_restricted_omp(r, h->stream)) != hipSuccess) return h->hip(e, "restricted omp");
+    (void)hipEventRecord(h->ev_prop[2], h->stream);
+    // full OMP on the signals the restricted code missed (count stays on the device)
+    const OmpTile tile = choose_tile(h, plan.maxKpad, s_max, false);
+    const int T = 16 * tile.tt;
+    OmpArgs oa{};
+    oa.desc = plan.omp_desc;
+    oa.items = nullptr;
+    oa.n_items = (int)((N + T - 1) / T);
+    oa.sig_list = fb_list;
+    oa.list_count = fb_cnt;
+    oa.m = m;
+    oa.mchunks = plan.mchunks;
+    oa.eps2 = 0.f;
+    oa.tau = SMDL_TAU;
+    oa.dep_tol = SMDL_DEP_TOL;
+    oa.idx = X.idx;
+    oa.coef = X.coef;
+    oa.nnz = X.nnz;
+    oa.res = nullptr;
+    oa.s_out = X.s_max;
+    if ((e = launch_omp(tile, plan.maxKpad, s_max, oa, oa.n_items, h->stream)) != hipSuccess) return h->hip(e, "fallback omp");
+    (void)hipEventRecord(h->ev_prop[3], h->stream);
+    int32_t cnt = 0;
+    if ((st = h->hip(hipMemcpyAsync(&cnt, fb_cnt, 4, hipMemcpyDeviceToHost, h->stream), "count")) != SMDL_OK) return st;
+    if ((st = h->hip(hipStreamSynchronize(h->stream), "proposed omp")) != SMDL_OK) return st;
+    for (int i = 0; i < 3; ++i) (void)hipEventElapsedTime(&h->prop_ms[i], h->ev_prop[i], h->ev_prop[i + 1]);
+    (void)hipGetLastError();
+    if (n_fallback) *n_fallback = cnt;
+    return SMDL_OK;
+}
+
+extern "C" smdl_status smdl_prop_phase_ms(smdl_t h, float* ms3) {
+    if (!h || !ms3) return SMDL_E_ARG;
+    for (int i = 0; i < 3; ++i) ms3[i] = h->prop_ms[i];
+    return SMDL_OK;
+}

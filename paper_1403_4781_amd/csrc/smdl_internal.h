@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP translation units of libsmdl (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "smdl.h"
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Hard limits of the kernels (checked on the host before any launch).
+constexpr int SMDL_MAX_M = 256;
+constexpr int SMDL_MAX_K = 1024;
+constexpr int SMDL_MAX_S = 16;
+// LDS one gfx950 workgroup may use (static + dynamic), minus a margin for static variables.
+constexpr size_t SMDL_LDS_BYTES = 160 * 1024 - 256;
+
+// Dictionaries are padded to Kpad atoms (multiple of 64) and m to mpad (multiple of 64) with
+// zeros.  The packed "fragment" layout feeds the 16x16x4 FP32 MFMA directly: for m-chunk c
+// (64 rows), atom block b (16 atoms), sub-step q (0..3) and lane l, the float4 at index
+// ((c * Kpad/16 + b) * 4 + q) * 64 + l holds D[atom 16b + l%16][row 64c + 16(l/16) + 4q .. +3].
+inline int pad64(int x) { return (x + 63) / 64 * 64; }
+
+// One dictionary and the signals coded against it.
+struct OmpDesc {
+    const float4* dfrag;  // packed fragments (mpad x Kpad floats)
+    const float* gram;    // Kpad x Kpad row-major Gram matrix (zero outside K x K)
+    const float* Y;       // signals (m floats each)
+    int64_t n;            // number of signals in this set
+    int64_t out0;         // output row of signal 0 of this set
+    int K, Kpad, s, pad_;
+};
+
+// A tile of up to T signals of one descriptor.
+struct OmpItem {
+    int32_t desc;
+    int32_t count;
+    int64_t first;
+};
+
+struct OmpArgs {
+    const OmpDesc* desc;     // descriptors (device)
+    const OmpItem* items;    // work items (device); NULL = one descriptor, item i covers T*i..
+    int n_items;             // number of items (or, with items == NULL, ceil(n / T))
+    int* queue;              // persistent work counter (device, zeroed before launch) or NULL
+    const int32_t* sig_list; // gather mode: signals to code are sig_list[0 .. *list_count)
+    const int32_t* list_count;
+    int m, mchunks;
+    float eps2, tau, dep_tol;
+    int32_t* idx;
+    float* coef;
+    int32_t* nnz;
+    float* res;              // optional
+    int s_out;               // ELL row stride of the output
+};
+
+// Tile configuration of the OMP kernel.
+struct OmpTile {
+    int lanes;   // lanes per signal: 16, 32, 64
+    int tt;      // work item = 16 * tt signals
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_pack_dict_m(const void* dev_pack_desc, int n_dict, int max_kpad, int m,
+                              int mchunks, hipStream_t st);
+hipError_t launch_gram_batched(const void* dev_gram_desc, int n_dict, int max_kpad, int mchunks,
+                               hipStream_t st);
+bool omp_tile_supported(OmpTile t, int Kpad, int s);
+hipError_t launch_omp(OmpTile t, int maxKpad, int maxS, const OmpArgs& a, int grid,
+                      hipStream_t st);
+size_t omp_lds_bytes(OmpTile t, int maxKpad);
+
+// Batched dictionary helpers (descriptor arrays live in device memory).
+struct PackDesc {
+    const float* D;   // m x K column-major
+    float4* dfrag;
+    int K, Kpad;
+};
+struct GramDesc {
+    const float4* dfrag;
+    float* G;
+    int Kpad, pad_;
+};
+
+// MOD descriptors.
+struct ModDesc {
+    const float* Y;          // signals of this set (m each), contiguous
+    const int32_t* idx;      // ELL codes of this set
+    const float* coef;
+    const int32_t* nnz;
+    int64_t n;               // signals
+    int64_t atom0;           // first global atom id of this dictionary
+    float* D;                // m x K dictionary (in/out)
+    double* A;               // Kpad x Kpad FP64 workspace (products)
+    double* W;               // (Kpad + m) x Kpad FP64 workspace (factorisation)
+    int K, Kpad;
+    int s_stride;            // ELL row stride
+    int pad_;
+};
+
+hipError_t launch_mod(const ModDesc* dev_desc, const ModDesc* host_desc, int n_desc, int m,
+                      int total_atoms, int64_t total_entries_cap, int32_t* cnt, int32_t* fill,
+                      int32_t* ptr, int32_t* list_sig, float* list_coef, int32_t* status,
+                      int max_kpad, hipStream_t st, bool per_desc);
+
+// Misc kernels.
+hipError_t launch_gather_columns(const float* Y, const int64_t* perm, int64_t N, int m, float* out,
+                                 int32_t* bad, hipStream_t st);
+hipError_t launch_init_from_columns_batched(const void* dev_init_desc, int n_dict, int max_k,
+                                            int m, hipStream_t st);
+struct InitDesc {
+    const float* Y;
+    float* D;
+    int K, pad_;
+};
+hipError_t launch_code_scales(const float* coef, const int32_t* nnz, int s_stride,
+                              const int64_t* offsets_dev, int L, double* scales, hipStream_t st);
+hipError_t launch_pool_scale(const float* Dloc, const int64_t* atom_off_dev, int L, int m,
+                             const double* scales, float* Ytil, int64_t total_atoms,
+                             hipStream_t st);
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
+hipError_t launch_fill_codes(int32_t* idx, float* coef, int32_t* nnz, int64_t N, int s_stride,
+                             hipStream_t st);

@@ -1,0 +1,206 @@
+"""GPU parity of the MOD update (teacher-forced: the same codes go into the GPU kernels and
+the FP64 oracle) and of the learning loops.
+
+The MOD bar: max_k ||d_k(gpu) - d_k(oracle)||_2 <= 1e-4 (unit atoms, FP32 output of an FP64
+solve from FP32 inputs).  Learning over several iterations is chaotic (a near-tie flip in one
+signal changes later dictionaries), so multi-iteration runs are compared on quantities that
+do not depend on individual decisions: final RMSE within 5e-3 relative of the oracle's (the
+trajectory itself is parity unpinned), exact agreement of the first iteration, and the
+structural properties of Algorithm 1.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1403_4781_amd import synth
+from tests.parity import compare, rmse, to_np
+
+pytestmark = pytest.mark.gpu
+
+D_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def h(dev):
+    import paper_1403_4781_amd as smdl
+    return smdl.Handle(0)
+
+
+def _t(a, dev, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to(dev)
+
+
+def _gpu_codes(codes, dev):
+    import paper_1403_4781_amd as smdl
+    return smdl.Codes(_t(codes.idx, dev, np.int32), _t(codes.coef, dev, np.float32), _t(codes.nnz, dev, np.int32))
+
+
+def _f32codes(codes):
+    """The oracle's codes rounded to FP32 (what the GPU receives), as oracle Codes."""
+    return oracle.Codes(codes.idx.copy(), codes.coef.astype(np.float32).astype(np.float64), codes.nnz.copy())
+
+
+@pytest.mark.parametrize("m,K,s,N", [(64, 128, 5, 2000), (64, 256, 8, 5000), (30, 60, 6, 1000),
+                                     (256, 512, 16, 3000), (64, 192, 12, 2500)])
+def test_mod_teacher_forced(h, dev, m, K, s, N):
+    print(f"case mod m={m} K={K} s={s} N={N}", flush=True)
+    D, Y, _ = synth.small_problem(3000 + K + s, m, K, min(s, 8), 0.02, N)
+    codes = _f32codes(oracle.omp(D, Y, s))
+    Dref, nu_ref, _ = oracle.mod_update(Y, codes, D)
+    Dg = _t(D, dev)
+    nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+    err = np.linalg.norm(Dg.cpu().numpy() - Dref, axis=1).max()
+    print(f"  max atom error {err:.3e} unused {nu}/{nu_ref}", flush=True)
+    assert nu == nu_ref
+    assert err <= D_TOL
+
+
+def test_mod_unused_atoms_and_ridge(h, dev):
+    """Unused atoms keep their value; two atoms used identically trigger the ridge retry."""
+    print("case mod ridge", flush=True)
+    rng = np.random.default_rng(3100)
+    m, K, N = 16, 64, 400
+    Y = rng.standard_normal((N, m)).astype(np.float32)
+    idx = np.full((N, 3), -1, np.int32)
+    coef = np.zeros((N, 3))
+    nnz = np.full(N, 3, np.int32)
+    for n in range(N):
+        idx[n] = [0, 1, 2 + n % 10]
+        c0 = np.float32(rng.standard_normal())
+        coef[n] = [c0, c0, rng.standard_normal()]
+    codes = oracle.Codes(idx, coef.astype(np.float32).astype(np.float64), nnz)
+    D = synth.gaussian_dictionary(rng, m, K).astype(np.float32)
+    Dref, nu_ref, ridge = oracle.mod_update(Y, codes, D)
+    assert ridge == 1 and nu_ref == K - 12
+    Dg = _t(D, dev)
+    nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+    Dn = Dg.cpu().numpy()
+    assert nu == nu_ref
+    np.testing.assert_array_equal(Dn[12:], D[12:])
+    assert np.linalg.norm(Dn[2:12] - Dref[2:12], axis=1).max() <= D_TOL
+    # the two tied atoms: direction of the ridge solution (same for both, up to 1e-3)
+    assert np.linalg.norm(Dn[:2] - Dref[:2], axis=1).max() <= 1e-3
+
+
+def test_mod_rejects_bad_indices(h, dev):
+    import paper_1403_4781_amd as smdl
+    print("case mod bad index", flush=True)
+    D, Y, _ = synth.small_problem(3200, 16, 32, 3, 0.01, 50)
+    codes = _f32codes(oracle.omp(D, Y, 3))
+    codes.idx[7, 1] = 40          # >= K
+    Dg = _t(D, dev)
+    with pytest.raises(smdl.SmdlError, match="E_ARG"):
+        h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+
+
+def test_learn_matches_oracle_statistically(h, dev):
+    """Oracle-scale workload: m=64, K=128, s=5, N=2000, 10 iterations, one dictionary."""
+    w = synth.oracle_scale()
+    Yp = w.Y[w.perm]                       # the seeded order; init = its first 128 signals
+    print("case learn oracle scale", flush=True)
+    Dg, Xg = h.learn(_t(Yp, dev), 128, 5, 10)
+    Dr, cr = oracle.learn(Yp, 128, 5, 10)
+    r_g = rmse(Dg.cpu().numpy(), Yp, *to_np(Xg))
+    r_o = rmse(Dr, Yp, cr.idx, cr.coef, cr.nnz)
+    print(f"  rmse gpu {r_g:.6e} oracle {r_o:.6e}", flush=True)
+    assert abs(r_g - r_o) <= 5e-3 * r_o
+    # iteration 0 is exact: the initial dictionary and its first coding
+    D0g, X0g = h.learn(_t(Yp, dev), 128, 5, 0)
+    D0r, c0r = oracle.learn(Yp, 128, 5, 0)
+    assert np.abs(D0g.cpu().numpy() - D0r).max() <= 1e-6
+    ora = oracle.omp(D0g.cpu().numpy(), Yp, 5, trace=True)
+    compare(to_np(X0g), ora, D0g.cpu().numpy(), Yp, label="learn iter0")
+
+
+def test_one_iteration_teacher_forced(h, dev):
+    """One alternation from a known dictionary: GPU (code + MOD) vs oracle (code + MOD) on
+    the GPU's codes: the dictionaries agree to the MOD bar."""
+    w = synth.oracle_scale()
+    Yp = w.Y[w.perm]
+    print("case learn 1 iteration", flush=True)
+    D1g, X1g = h.learn(_t(Yp, dev), 128, 5, 1)
+    D0 = (Yp[:128] / np.linalg.norm(Yp[:128].astype(np.float64), axis=1, keepdims=True))
+    c0 = oracle.omp(D0, Yp, 5, trace=True)
+    # the GPU's first coding must agree with the oracle's on every signal for exact forcing
+    gi0 = h.omp_code(_t(D0, dev), _t(Yp, dev), 5)
+    compare(to_np(gi0), c0, D0, Yp, label="iter1 coding")
+    codes = oracle.Codes(*[a.copy() for a in (to_np(gi0)[0], to_np(gi0)[1], to_np(gi0)[2])])
+    D1r, _, _ = oracle.mod_update(Yp, codes, D0.astype(np.float32))
+    assert np.linalg.norm(D1g.cpu().numpy() - D1r, axis=1).max() <= D_TOL
+
+
+def _sm_setup(N=8000, L=4):
+    w = synth.patch_scale(N=N, L=L, iters=3)
+    return w
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2])
+def test_split_merge_structure_and_quality(h, dev, flags):
+    """Algorithm 1 on a reduced patch-scale workload (N=8000, L=4, 3+3 iterations): local
+    dictionaries and scales agree with per-subset runs of the standard alternation; final
+    RMSE within 1e-3 relative of the oracle's; batched, per-subset and graph-free runs agree."""
+    import paper_1403_4781_amd as smdl
+    w = _sm_setup()
+    print(f"case split-merge flags={flags}", flush=True)
+    perm = torch.from_numpy(w.perm).to(dev)
+    D, X, Dl, sc = h.split_merge_learn(_t(w.Y, dev), perm, w.offsets, w.K_local, w.s_local, w.K,
+                                       w.iters_local, w.iters_merge, w.s_merge, w.s_final, flags=flags,
+                                       local=True)
+    Dn = D.cpu().numpy()
+    Dln = Dl.cpu().numpy()
+    assert Dln.shape == (w.K_local.sum(), 64)
+    np.testing.assert_allclose(np.linalg.norm(Dn, axis=1), 1.0, atol=1e-5)
+    # scales are the Frobenius norms of the local final codes: recompute from a GPU learn
+    for t in range(w.L):
+        sub = w.Y[w.perm[w.offsets[t]:w.offsets[t + 1]]]
+        Dt, Xt = h.learn(_t(sub, dev), int(w.K_local[t]), int(w.s_local[t]), w.iters_local)
+        rel = np.linalg.norm(Dt.cpu().numpy() - Dln[256 * t:256 * (t + 1)], axis=1).max()
+        assert rel <= 1e-3, rel
+        sct = float(np.sqrt((Xt.coef.double() ** 2).sum().item()))
+        assert abs(sct - sc[t]) <= 1e-4 * sct
+    Do, co, _, sco = oracle.split_merge(w.Y, w.perm, w.offsets, w.K_local, w.s_local, w.K, w.iters_local,
+                                        w.iters_merge, w.s_merge, w.s_final)
+    r_g = rmse(Dn, w.Y, *to_np(X))
+    r_o = rmse(Do, w.Y, co.idx, co.coef, co.nnz)
+    print(f"  rmse gpu {r_g:.6e} oracle {r_o:.6e}; scales gpu {sc[:2]} oracle {sco[:2]}", flush=True)
+    assert abs(r_g - r_o) <= 5e-3 * r_o
+    np.testing.assert_allclose(sc, sco, rtol=1e-3)
+    # final codes are plain OMP of all N with the merged dictionary
+    ora = oracle.omp(Dn, w.Y[:1500], w.s_final, trace=True)
+    compare((to_np(X)[0][:1500], to_np(X)[1][:1500], to_np(X)[2][:1500]), ora, Dn, w.Y[:1500],
+            label=f"split-merge final flags={flags}")
+
+
+def test_batched_uneven_subsets(h, dev):
+    """Uneven subsets with different K_t and s_t in one persistent launch per stage
+    (batched-split workload shape, reduced): iteration-0 codes of every subset match the
+    oracle and the learned local dictionaries match per-subset launches."""
+    g = synth.rng_streams(77)
+    L = 6
+    sizes = synth.uneven_sizes(g[0], L, 300, 1200)
+    Kl = np.array([64, 128, 192, 256, 64, 128], np.int32)
+    sl = np.array([4, 8, 12, 8, 12, 4], np.int32)
+    w = synth.make_workload("batched_small", seed=78, m=64, K0=256, s0=8, sigma=0.02, N=int(sizes.sum()),
+                            sizes=sizes, K_local=Kl, s_local=sl, K=128, iters_local=2, iters_merge=1,
+                            s_merge=4, s_final=8)
+    perm = torch.from_numpy(w.perm).to(dev)
+    Yt = _t(w.Y, dev)
+    res = {}
+    for flags in (0, 1):
+        print(f"case batched uneven flags={flags}", flush=True)
+        D, X, Dl, sc = h.split_merge_learn(Yt, perm, w.offsets, Kl, sl, w.K, 2, 1, 4, 8, flags=flags, local=True)
+        res[flags] = (Dl.cpu().numpy(), sc)
+    ao = np.concatenate([[0], np.cumsum(Kl)])
+    for t in range(L):
+        a = res[0][0][ao[t]:ao[t + 1]]
+        b = res[1][0][ao[t]:ao[t + 1]]
+        assert np.linalg.norm(a - b, axis=1).max() <= 1e-3
+    np.testing.assert_allclose(res[0][1], res[1][1], rtol=1e-4)
+    # iteration 0 of every subset against the oracle
+    for t in range(L):
+        sub = w.Y[w.perm[w.offsets[t]:w.offsets[t + 1]]]
+        D0 = sub[:Kl[t]] / np.linalg.norm(sub[:Kl[t]].astype(np.float64), axis=1, keepdims=True)
+        ora = oracle.omp(D0, sub, int(sl[t]), trace=True)
+        Xg = h.omp_code(_t(D0, dev), _t(sub, dev), int(sl[t]))
+        compare(to_np(Xg), ora, D0, sub, label=f"subset {t} K{Kl[t]} s{sl[t]}")

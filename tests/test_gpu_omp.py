@@ -1,0 +1,162 @@
+"""GPU parity of the Gram kernel and the fused OMP kernel against the FP64 oracle.
+
+Covers every lanes-per-signal / signals-per-item tile the library instantiates for the
+tested shapes, ragged signal counts, m not a multiple of 4 or 64, K not a multiple of 64,
+both OMP forms (sparsity- and error-constrained), degenerate signals, and the full-size
+patch-scale workload (m=64, K=256, s=8, N=100000) on sampled signals.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1403_4781_amd import synth
+from tests.parity import compare, rmse, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h(dev):
+    import paper_1403_4781_amd as smdl
+    return smdl.Handle(0)
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+@pytest.mark.parametrize("m,K", [(64, 256), (30, 60), (256, 1024), (16, 50)])
+def test_gram_matches_fp64(h, dev, m, K):
+    print(f"case gram m={m} K={K}", flush=True)
+    D, _, _ = synth.small_problem(100 + K, m, K, 3, 0.0, 4)
+    G = h.gram(_t(D, dev)).cpu().numpy()
+    Gr = D.astype(np.float64) @ D.astype(np.float64).T
+    assert np.abs(G - Gr).max() <= 1e-5 * max(1.0, np.abs(Gr).max())
+
+
+SHAPES = [
+    # m, K, s, N, sigma
+    (64, 128, 5, 2000, 0.01),     # oracle-scale workload shape
+    (64, 256, 8, 3001, 0.02),     # patch scale, ragged N
+    (30, 60, 6, 777, 0.01),       # Section 3.1 sizes (m=30, K=60, s=6)
+    (64, 64, 4, 500, 0.02),
+    (64, 192, 12, 1200, 0.02),
+    (256, 512, 16, 300, 0.02),
+    (256, 1024, 16, 200, 0.02),
+    (16, 50, 3, 333, 0.0),
+]
+
+
+@pytest.mark.parametrize("m,K,s,N,sigma", SHAPES)
+def test_omp_parity_all_tiles(h, dev, m, K, s, N, sigma):
+    D, Y, _ = synth.small_problem(1000 + m + K + s, m, K, min(s, 8), sigma, N)
+    ora = oracle.omp(D, Y, s, trace=True)
+    Dt, Yt = _t(D, dev), _t(Y, dev)
+    Kpad = (K + 63) // 64 * 64
+    tried = 0
+    for lanes in (16, 32, 64):
+        for spi in (16, 32, 64):
+            try:
+                h.set_tile(K, s, lanes, spi)
+            except Exception:
+                continue
+            print(f"case omp m={m} K={K} s={s} N={N} lanes={lanes} spi={spi}", flush=True)
+            X = h.omp_code(Dt, Yt, s)
+            compare(to_np(X), ora, D, Y, label=f"m{m} K{K} s{s} lanes{lanes} spi{spi}")
+            tried += 1
+    assert tried >= 1, (m, K, s, Kpad)
+
+
+def test_error_constrained_form(h, dev):
+    """eps > 0: stop once ||r|| <= eps (Section 3.2.2), cap s_max."""
+    D, Y, _ = synth.small_problem(2001, 64, 256, 6, 0.05, 2000)
+    for eps in (0.6, 1.5):
+        print(f"case omp-eps eps={eps}", flush=True)
+        ora = oracle.omp(D, Y, 16, eps=eps, trace=True)
+        X, r = h.omp_code(_t(D, dev), _t(Y, dev), 16, eps=eps, res_norm=True)
+        compare(to_np(X), ora, D, Y, eps=eps, label=f"eps{eps}")
+        rn = r.cpu().numpy()
+        gi, gc, gn = to_np(X)
+        ok = gn < 16
+        # the returned residual norm is within the target where the loop stopped early
+        assert (rn[ok] <= eps * (1 + 1e-4)).all()
+
+
+def test_degenerate_signals(h, dev):
+    """Zero signals give empty codes; a signal equal to an atom is coded by that atom;
+    duplicate atoms are never both chosen; N = 1 and N = 0 work."""
+    D, Y, _ = synth.small_problem(2002, 64, 128, 4, 0.01, 40)
+    Y[:5] = 0.0
+    Y[5] = 2.5 * D[17]
+    Ddup = np.vstack([D, D[:8]])
+    for DD in (D, Ddup):
+        K = DD.shape[0]
+        print(f"case degenerate K={K}", flush=True)
+        X = h.omp_code(_t(DD, dev), _t(Y, dev), 6)
+        gi, gc, gn = to_np(X)
+        assert (gn[:5] == 0).all() and (gi[:5] == -1).all() and (gc[:5] == 0).all()
+        assert gn[5] == 1 and gi[5, 0] == 17 and abs(gc[5, 0] - 2.5) < 1e-5
+        ora = oracle.omp(DD, Y, 6, trace=True)
+        compare((gi, gc, gn), ora, DD, Y, label=f"degenerate K{K}")
+        if K > 128:
+            for n in range(40):
+                sel = set(gi[n, :gn[n]])
+                for j in range(8):
+                    assert not ({j, 128 + j} <= sel)
+    print("case N=1", flush=True)
+    X = h.omp_code(_t(D, dev), _t(Y[6:7], dev), 4)
+    assert X.nnz.shape == (1,)
+    print("case N=0", flush=True)
+    X = h.omp_code(_t(D, dev), _t(Y[:0], dev), 4)
+    assert X.nnz.shape == (0,)
+
+
+def test_output_stride_larger_than_sparsity(h, dev):
+    import paper_1403_4781_amd as smdl
+    D, Y, _ = synth.small_problem(2003, 64, 128, 4, 0.01, 100)
+    print("case stride", flush=True)
+    out = smdl.Codes.empty(100, 12, dev)
+    out.idx.fill_(7)
+    out.coef.fill_(3.0)
+    X = h.omp_code(_t(D, dev), _t(Y, dev), 4, out=out)
+    gi, gc, gn = to_np(X)
+    assert (gi[:, 4:] == -1).all() and (gc[:, 4:] == 0).all()
+    ora = oracle.omp(D, Y, 4, trace=True)
+    compare((gi[:, :4], gc[:, :4], gn), ora, D, Y, label="stride12")
+
+
+def test_argument_errors(h, dev):
+    import paper_1403_4781_amd as smdl
+    D, Y, _ = synth.small_problem(2004, 64, 128, 4, 0.01, 10)
+    Dt, Yt = _t(D, dev), _t(Y, dev)
+    print("case argument errors", flush=True)
+    with pytest.raises(smdl.SmdlError):
+        h.omp_code(Dt, Yt, 17)          # s > 16
+    with pytest.raises(smdl.SmdlError):
+        h.omp_code(Dt, Yt, 4, eps=-1.0)
+    with pytest.raises(smdl.SmdlError):
+        h.omp_code(Dt, Yt, 4, out=smdl.Codes.empty(10, 2, dev))   # stride < s
+    with pytest.raises(smdl.SmdlError):
+        h.omp_code(_t(np.zeros((1100, 64)), dev), Yt, 4)          # K > 1024
+
+
+def test_full_size_patch_workload_sampled(h, dev):
+    """m=64, K=256, s=8, N=100000 in the launch configuration the benchmark times; 3000
+    sampled signals are compared with the oracle one by one, and every code is checked for
+    the invariants that hold at any size (support size, distinct atoms, residual bound)."""
+    w = synth.patch_scale()
+    D = synth.gaussian_dictionary(np.random.default_rng(7), 64, 256).astype(np.float32)
+    Yt = _t(w.Y, dev)
+    Dt = _t(D, dev)
+    print("case full-size N=100000", flush=True)
+    X, r = h.omp_code(Dt, Yt, 8, res_norm=True)
+    gi, gc, gn = to_np(X)
+    assert (gn == 8).mean() > 0.999
+    srt = np.sort(np.where(gi >= 0, gi, 10 ** 6), axis=1)
+    assert not ((srt[:, 1:] == srt[:, :-1]) & (srt[:, 1:] < 10 ** 6)).any()
+    rs = np.random.default_rng(8).choice(w.N, 3000, replace=False)
+    ora = oracle.omp(D, w.Y[rs], 8, trace=True)
+    compare((gi[rs], gc[rs], gn[rs]), ora, D, w.Y[rs], label="N=1e5 sampled")
+    rr = np.linalg.norm(w.Y[rs].astype(np.float64) - np.einsum('ns,nsm->nm', gc[rs], D.astype(np.float64)[np.maximum(gi[rs], 0)]), axis=1)
+    np.testing.assert_allclose(r.cpu().numpy()[rs], rr, rtol=1e-3, atol=1e-4)

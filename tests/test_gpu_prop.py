@@ -1,0 +1,189 @@
+"""GPU parity of the learned support proposer: logits and gradients against the FP64 oracle
+with the same BF16 rounding points, a training step, the exact invariants of the restricted
+OMP with fallback, proposer-path parity against the oracle, and the gain of a trained network
+over an untrained one.
+
+Tolerances (derived from the arithmetic): FP32 accumulation against FP64 leaves ~1e-6 relative
+error, but a hidden activation whose FP32 and FP64 values straddle a BF16 rounding boundary
+rounds differently (one BF16 ulp, 2^-8 relative); such flips are rare (about one unit in 10^3)
+and bound the logits and gradients to ~1e-3 relative in Frobenius norm.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1403_4781_amd import synth
+from tests.parity import compare, to_np
+
+pytestmark = pytest.mark.gpu
+
+REL = 2e-3
+
+
+@pytest.fixture(scope="module")
+def h(dev):
+    import paper_1403_4781_amd as smdl
+    return smdl.Handle(0)
+
+
+def _t(a, dev, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to(dev)
+
+
+def _codes_t(c, dev):
+    import paper_1403_4781_amd as smdl
+    return smdl.Codes(_t(c.idx, dev, np.int32), _t(c.coef, dev), _t(c.nnz, dev, np.int32))
+
+
+def _relfro(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_logits_parity(h, dev):
+    widths = [64, 128, 96, 256]
+    Ws, bs = synth.mlp_init(widths, seed=11)
+    D, Y, _ = synth.small_problem(4000, 64, 256, 8, 0.02, 777)
+    print("case logits", flush=True)
+    p = h.proposer(Ws, bs)
+    lg = p.logits(_t(Y, dev)).cpu().numpy()
+    ref = oracle.mlp_forward(Ws, bs, Y)
+    e = _relfro(lg, ref)
+    print(f"  logits rel {e:.2e} max abs {np.abs(lg - ref).max():.2e}", flush=True)
+    assert e <= REL
+
+
+def test_gradient_parity(h, dev):
+    widths = [64, 128, 96, 256]
+    Ws, bs = synth.mlp_init(widths, seed=12)
+    D, Y, _ = synth.small_problem(4001, 64, 256, 8, 0.02, 300)     # B not a multiple of 32
+    labels = oracle.omp(D, Y, 8)
+    print("case gradients", flush=True)
+    p = h.proposer(Ws, bs)
+    loss, dW, db = p.grad(_t(Y, dev), _codes_t(labels, dev))
+    lref, dWr, dbr = oracle.mlp_grad(Ws, bs, Y, oracle.multi_hot(labels, 256))
+    print(f"  loss gpu {loss:.6f} oracle {lref:.6f}", flush=True)
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    for l in range(3):
+        ew, eb = _relfro(dW[l].cpu().numpy(), dWr[l]), _relfro(db[l].cpu().numpy(), dbr[l])
+        print(f"  layer {l}: dW rel {ew:.2e} db rel {eb:.2e}", flush=True)
+        assert ew <= REL and eb <= REL
+
+
+def test_training_step_and_loss_decrease(h, dev):
+    widths = [64, 128, 96, 256]
+    Ws, bs = synth.mlp_init(widths, seed=13)
+    D, Y, _ = synth.small_problem(4002, 64, 256, 8, 0.02, 4096)
+    labels = oracle.omp(D, Y, 8)
+    print("case train step", flush=True)
+    p = h.proposer(Ws, bs)
+    p.train(_t(Y[:512], dev), _codes_t(oracle.Codes(labels.idx[:512], labels.coef[:512], labels.nnz[:512]), dev),
+            epochs=1, batch=512, lr=1e-3)
+    W1, b1 = p.weights()
+    # oracle: same step in FP64
+    _, dWr, dbr = oracle.mlp_grad(Ws, bs, Y[:512], oracle.multi_hot(labels, 256)[:512])
+    for l in range(3):
+        w = Ws[l].astype(np.float64).ravel().copy()
+        mom, vel = np.zeros_like(w), np.zeros_like(w)
+        oracle.adam(w, dWr[l].ravel().copy(), mom, vel, 1, lr=1e-3)
+        dg = W1[l].astype(np.float64).ravel() - Ws[l].astype(np.float64).ravel()
+        do = w - Ws[l].astype(np.float64).ravel()
+        e = _relfro(dg, do)
+        print(f"  layer {l} update rel {e:.2e}", flush=True)
+        assert e <= 0.05     # Adam's first step is ~lr*sign(g): a tiny |g| may flip sign
+    print("case train epochs", flush=True)
+    p2 = h.proposer(Ws, bs)
+    losses = p2.train(_t(Y, dev), _codes_t(labels, dev), epochs=5, batch=256, lr=2e-3, shuffle_seed=5)
+    print(f"  losses {losses}", flush=True)
+    assert losses[-1] < 0.8 * losses[0]
+
+
+def test_restricted_invariants(h, dev):
+    """eps_fallback = 0: every signal falls back, the codes equal plain OMP exactly;
+    eps_fallback = inf: none falls back and every chosen atom is a candidate."""
+    widths = [64, 128, 256]
+    Ws, bs = synth.mlp_init(widths, seed=14)
+    D, Y, _ = synth.small_problem(4003, 64, 256, 8, 0.02, 1000)
+    Dt, Yt = _t(D, dev), _t(Y, dev)
+    p = h.proposer(Ws, bs)
+    print("case restricted eps=0", flush=True)
+    X0, fb0, n0, _ = h.omp_code_proposed(p, Dt, Yt, 8, 24, 0.0)
+    Xp = h.omp_code(Dt, Yt, 8)
+    assert n0 == 1000 and int(fb0.sum()) == 1000
+    for a, b in zip(to_np(X0), to_np(Xp)):
+        np.testing.assert_array_equal(a, b)
+    print("case restricted eps=inf", flush=True)
+    Xi, fbi, ni, cand = h.omp_code_proposed(p, Dt, Yt, 8, 24, float("inf"), want_cand=True)
+    assert ni == 0 and int(fbi.sum()) == 0
+    gi, gc, gn = to_np(Xi)
+    cn = cand.cpu().numpy()
+    assert (np.diff(cn, axis=1) > 0).all()
+    for n in range(1000):
+        assert set(gi[n, :gn[n]]) <= set(cn[n])
+
+
+def test_proposed_path_parity(h, dev):
+    """GPU proposer path vs the oracle's (its own FP64 logits with BF16 points): candidate sets
+    agree away from a top-k boundary tie, and the resulting codes pass the parity bar."""
+    widths = [64, 128, 256]
+    Ws, bs = synth.mlp_init(widths, seed=15)
+    D, Y, _ = synth.small_problem(4004, 64, 256, 8, 0.02, 2000)
+    Dt, Yt = _t(D, dev), _t(Y, dev)
+    p = h.proposer(Ws, bs)
+    plain = oracle.omp(D, Y, 8)
+    eps_fb = 1.1 * float(np.sqrt(np.mean(plain.res_norm ** 2)))
+    print("case proposed parity", flush=True)
+    X, fb, nfb, cand = h.omp_code_proposed(p, Dt, Yt, 8, 24, eps_fb, want_cand=True)
+    lg = oracle.mlp_forward(Ws, bs, Y)
+    ora = oracle.propose_code(D, Y, lg, 24, 8, eps_fb)
+    srt = -np.sort(-lg, axis=1)
+    boundary = (srt[:, 23] - srt[:, 24]) < 1e-3 * np.maximum(np.abs(srt[:, 23]), 1.0)
+    cn = cand.cpu().numpy()
+    same_c = (cn == ora.cand).all(axis=1)
+    print(f"  candidates agree {same_c[~boundary].mean():.5f} boundary {boundary.sum()} fallbacks gpu {nfb} oracle {int(ora.fell_back.sum())}", flush=True)
+    assert same_c[~boundary].mean() >= 0.999
+    # codes: on signals with identical candidate sets and fallback decisions, compare against an
+    # oracle trace of the same restricted problem
+    fbg = fb.cpu().numpy().astype(bool)
+    ok = same_c & (fbg == ora.fell_back.astype(bool))
+    assert ok.mean() >= 0.99
+    gi, gc, gn = to_np(X)
+    agree = ok & (gn == ora.nnz) & (np.where(np.arange(8)[None] < gn[:, None], gi, -1) ==
+                                    np.where(np.arange(8)[None] < ora.nnz[:, None], ora.idx, -1)).all(axis=1)
+    print(f"  code agreement {agree[ok].mean():.5f}", flush=True)
+    assert agree[ok].mean() >= 0.999
+
+
+def test_trained_network_gains(h, dev):
+    """What training buys: on fresh signals, the trained proposer's candidates contain the
+    plain-OMP support far more often than an untrained network's, so far fewer signals need
+    the full-OMP fallback at the same residual target, at equal representation error."""
+    widths = [64, 256, 256, 256]
+    Ws, bs = synth.mlp_init(widths, seed=16)
+    g = synth.rng_streams(4005)
+    D = synth.gaussian_dictionary(g[0], 64, 256).astype(np.float32)
+    Ytr, _, _ = synth.sparse_signals(g[1], D.astype(np.float64), 8, 0.02, 30000)
+    Yev, _, _ = synth.sparse_signals(g[2], D.astype(np.float64), 8, 0.02, 5000)
+    Dt = _t(D, dev)
+    print("case trained gains", flush=True)
+    lab = h.omp_code(Dt, _t(Ytr, dev), 8)
+    plain, rn = h.omp_code(Dt, _t(Yev, dev), 8, res_norm=True)
+    eps_fb = 1.1 * float(torch.sqrt((rn.double() ** 2).mean()).item())
+    untrained = h.proposer(Ws, bs)
+    trained = h.proposer(Ws, bs)
+    losses = trained.train(_t(Ytr, dev), lab, epochs=8, batch=1024, lr=2e-3, shuffle_seed=3)
+    print(f"  losses {losses}", flush=True)
+    res = {}
+    for name, p in (("untrained", untrained), ("trained", trained)):
+        X, fb, nfb, cand = h.omp_code_proposed(p, Dt, _t(Yev, dev), 8, 24, eps_fb, want_cand=True)
+        gi, gc, gn = to_np(X)
+        pi, pc, pn = to_np(plain)
+        cn = cand.cpu().numpy()
+        recall = np.mean([len(set(pi[n, :pn[n]]) & set(cn[n])) / max(pn[n], 1) for n in range(5000)])
+        from tests.parity import rmse
+        r = rmse(D, Yev, gi, gc, gn) / rmse(D, Yev, pi, pc, pn)
+        res[name] = (nfb / 5000, recall, r)
+        print(f"  {name}: fallback {nfb / 5000:.4f} recall {recall:.4f} rmse ratio {r:.5f}", flush=True)
+    assert res["trained"][1] > res["untrained"][1] + 0.3
+    assert res["trained"][0] < 0.5 * res["untrained"][0]
+    assert 0.99 <= res["trained"][2] <= 1.01
