@@ -42,6 +42,20 @@ def omp_bytes_per_signal(m: int, s: int) -> int:
     return 4 * m + 8 * s + 4
 
 
+def measured_traffic():
+    """HBM bytes per launch of the plain OMP pass from the committed rocprofv3 PMC summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "omp_fused_traffic.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_1403_4781_amd", "csrc", "omp_kernel.h"), "rb") as f:
+            sha = hashlib.sha1(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("omp_kernel_sha1") == sha else None
+
+
 def cpu_baseline(w, sample_subsets: int, sample_n: int, iters: int):
     """The FP64 oracle on a bounded sample of the same workload, timed on the host cores."""
     import oracle
@@ -74,7 +88,9 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=5000)
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--omp-only", type=int, default=0,
-                    help="only run the final-coding kernel this many times (for profilers)")
+                    help="only run the plain OMP coding of the 100000 signals this many times (for profilers)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -85,6 +101,16 @@ def main():
     from paper_1403_4781_amd import synth
 
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_mib": args.copy_calib, "bytes_read_per_copy": 4 * n,
+                          "bytes_written_per_copy": 4 * n}))
+        return
     w = synth.patch_scale(N=100000, L=20, iters=args.iters)
     Ytr = synth.fresh_signals(w, synth.STREAM_TRAIN, 200000, 8, 0.02)
     Yev = synth.fresh_signals(w, synth.STREAM_EVAL, 100000, 8, 0.02)
@@ -188,7 +214,8 @@ def main():
         "train_loss": last["losses"][-1] if last["losses"] else None,
         "roofline": {"kernel": "omp_fused (plain OMP pass, N=100000)", "bound": "alu",
                      "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s", "frac": achieved / 157.3,
-                     "traffic": None, "per_signal_flops": f_sig,
+                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch (HBM read + write)",
+                     "per_signal_flops": f_sig,
                      "per_signal_bytes": omp_bytes_per_signal(64, 8)},
     }
     if not args.no_cpu_baseline:

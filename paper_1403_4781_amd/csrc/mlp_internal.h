@@ -14,9 +14,13 @@ struct GemmArgs {
     int relu;
     float* out_f32;             // optional
     uint16_t* out_bf16;         // optional
+    int ksplit;                 // > 1: blockIdx.z takes K/ksplit of the reduction and adds its
+                                // partial into out_f32 with atomics (out_f32 zeroed beforehand)
 };
 
 hipError_t launch_gemm(const GemmArgs& g, bool AT, bool BT, bool big, hipStream_t st);
+hipError_t launch_transpose_bf16(const uint16_t* in, int rows, int cols, uint16_t* out, hipStream_t st);
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_prep_input(const float* Y, int64_t B, int m, int mpad, int64_t Bpad, const int32_t* rows,
                              uint16_t* h0, hipStream_t st);
 hipError_t launch_bce(const float* z, int64_t B, int64_t Bpad, int K, const int32_t* lidx, const int32_t* lnnz,

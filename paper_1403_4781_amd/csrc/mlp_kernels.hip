@@ -28,6 +28,8 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDSK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int kspan = g.ksplit > 1 ? g.K / g.ksplit : g.K;
+    const int kbeg = g.ksplit > 1 ? (int)blockIdx.z * kspan : 0;
     constexpr int WM = BM / 2, WN = BN / 2;      // per-wave tile (2 x 2 waves)
     constexpr int FM = WM / 16, FN = WN / 16;
     const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
@@ -37,7 +39,7 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    for (int k0 = kbeg; k0 < kbeg + kspan; k0 += BK) {
         // ---- stage A (BM x BK) and B (BN x BK) into LDS as [row][k]
         auto stage = [&](const uint16_t* __restrict__ src, int ld, int rows, int r0, bool trans,
                          uint16_t* dst, int R) {
@@ -94,6 +96,10 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
                     if (!(bf2f(g.mask_bf16[(int64_t)row * g.ldmask + col]) > 0.f)) v = 0.f;
                 }
                 if (g.relu) v = fmaxf(v, 0.f);
+                if (g.ksplit > 1) {
+                    atomicAdd(&g.out_f32[(int64_t)row * g.ldc + col], v);
+                    continue;
+                }
                 if (g.out_f32) g.out_f32[(int64_t)row * g.ldc + col] = v;
                 if (g.out_bf16) g.out_bf16[(int64_t)row * g.ldc + col] = f2bf(v);
             }
@@ -161,13 +167,24 @@ __global__ __launch_bounds__(256) void bce_kernel(const float* __restrict__ z, i
     if (threadIdx.x == 0) loss_part[b] = red[0];
 }
 
-// out[j] = sum_b x[b][j] (FP32 input, FP64 accumulation in fixed order).
-__global__ void colsum_kernel(const float* __restrict__ x, int64_t B, int N, float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// out[j] = sum_b x[b][j] (FP32 input, FP64 accumulation in a fixed order): block = 16 columns
+// x 64 row slices; each thread sums every 64th row of its column, then the 64 partials are
+// added in slice order.
+__global__ __launch_bounds__(1024) void colsum_kernel(const float* __restrict__ x, int64_t B, int N,
+                                                      float* __restrict__ out) {
+    __shared__ double part[64][16];
+    const int c = threadIdx.x & 15, sl = threadIdx.x >> 4;
+    const int j = blockIdx.x * 16 + c;
     double s = 0.0;
-    for (int64_t b = 0; b < B; ++b) s += x[b * N + j];
-    out[j] = (float)s;
+    if (j < N)
+        for (int64_t b = sl; b < B; b += 64) s += x[b * N + j];
+    part[sl][c] = s;
+    __syncthreads();
+    if (sl == 0 && j < N) {
+        double t = 0.0;
+        for (int q = 0; q < 64; ++q) t += part[q][c];
+        out[j] = (float)t;
+    }
 }
 
 __global__ void sum_f64_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
@@ -216,6 +233,24 @@ __global__ void to_bf16_kernel(const float* __restrict__ w, int64_t n, int cols,
     }
 }
 
+// out[c][r] = in[r][c] for a rows x cols BF16 matrix, 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void transpose_bf16_kernel(const uint16_t* __restrict__ in, int rows, int cols,
+                                                             uint16_t* __restrict__ out) {
+    __shared__ uint16_t tile[64][66];
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4)
+        tile[r][tx] = (r0 + r < rows && c0 + tx < cols) ? in[(int64_t)(r0 + r) * cols + c0 + tx] : (uint16_t)0;
+    __syncthreads();
+    for (int c = ty; c < 64; c += 4)
+        if (c0 + c < cols && r0 + tx < rows) out[(int64_t)(c0 + c) * rows + r0 + tx] = tile[tx][c];
+}
+
+__global__ void zero_f32_kernel(float* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
 inline int grid_n(int64_t n) {
     int64_t g = (n + 255) / 256;
     return (int)(g > 8192 ? 8192 : (g < 1 ? 1 : g));
@@ -223,15 +258,28 @@ inline int grid_n(int64_t n) {
 
 }  // namespace
 
+hipError_t launch_transpose_bf16(const uint16_t* in, int rows, int cols, uint16_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(transpose_bf16_kernel, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, st, in, rows,
+                       cols, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(grid_n(n)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm(const GemmArgs& g, bool AT, bool BT, bool big, hipStream_t st) {
+    const int ks = g.ksplit > 1 ? g.ksplit : 1;
+    if (ks > 1 && (g.K % (32 * ks) || !g.out_f32 || g.out_bf16)) return hipErrorInvalidValue;
     if (big) {
-        dim3 grid((g.N + 127) / 128, (g.M + 127) / 128);
+        dim3 grid((g.N + 127) / 128, (g.M + 127) / 128, ks);
         if (!AT && !BT) hipLaunchKernelGGL((gemm_bf16<128, 128, false, false>), grid, dim3(256), 0, st, g);
         else if (AT && BT) hipLaunchKernelGGL((gemm_bf16<128, 128, true, true>), grid, dim3(256), 0, st, g);
         else if (!AT && BT) hipLaunchKernelGGL((gemm_bf16<128, 128, false, true>), grid, dim3(256), 0, st, g);
         else return hipErrorInvalidValue;
     } else {
-        dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+        dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, ks);
         if (!AT && !BT) hipLaunchKernelGGL((gemm_bf16<64, 64, false, false>), grid, dim3(256), 0, st, g);
         else if (AT && BT) hipLaunchKernelGGL((gemm_bf16<64, 64, true, true>), grid, dim3(256), 0, st, g);
         else if (!AT && BT) hipLaunchKernelGGL((gemm_bf16<64, 64, false, true>), grid, dim3(256), 0, st, g);
@@ -259,7 +307,7 @@ hipError_t launch_bce(const float* z, int64_t B, int64_t Bpad, int K, const int3
 }
 
 hipError_t launch_colsum(const float* x, int64_t B, int N, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, st, x, B, N, out);
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 15) / 16), dim3(1024), 0, st, x, B, N, out);
     return hipGetLastError();
 }
 

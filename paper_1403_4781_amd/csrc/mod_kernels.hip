@@ -14,7 +14,7 @@
 
 namespace {
 
-constexpr int NB = 32;          // Cholesky panel width
+constexpr int NB = 16;          // Cholesky panel width
 constexpr double PIV_TOL = 1e-12;
 constexpr double RIDGE = 1e-10;
 
@@ -147,61 +147,75 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
     }
 }
 
-// One block (256 threads) per dictionary.
+// One block (512 threads) per dictionary.
 // status[4*t + 0] = unused atoms (this call), [1] |= ridge used, [2] |= failed; the caller zeroes
 // the status array before a sequence of updates.
-__global__ __launch_bounds__(256) void chol_solve_kernel(const ModDesc* __restrict__ md, int m,
-                                                         int32_t* __restrict__ status) {
+constexpr int CT = 512;                       // threads of the solve
+constexpr int PANEL_LDS_ROWS = 896;           // panel rows kept in LDS (896 x 16 doubles = 112 KB)
+
+__global__ __launch_bounds__(CT) void chol_solve_kernel(const ModDesc* __restrict__ md, int m,
+                                                        int32_t* __restrict__ status) {
     const ModDesc d = md[blockIdx.x];
     const int tid = threadIdx.x;
     const int Kp = d.Kpad;
-    const int64_t ld = Kp + m;          // rows of M
+    const int64_t ld = Kp + m;          // rows of M = [A; B]
     const double* P = d.A;              // pristine products
     double* W = d.W;                    // factorisation workspace
     __shared__ double Ld[NB][NB + 1];
+    __shared__ double panel[PANEL_LDS_ROWS * NB];
     __shared__ double diag0[SMDL_MAX_K];
     __shared__ unsigned char active[SMDL_MAX_K];
-    __shared__ int s_fail;
-    __shared__ double s_red[256];
-    __shared__ int s_cnt[256];
+    __shared__ int s_fail, s_failed_final;
+    __shared__ double s_red[CT / 64];
+    __shared__ int s_cnt[CT / 64];
 
     // max active diagonal and unused count
     double mx = 0.0;
     int unused = 0;
-    for (int a = tid; a < Kp; a += 256) {
+    for (int a = tid; a < Kp; a += CT) {
         const double v = P[(int64_t)a * ld + a];
         active[a] = v > 0.0;
         if (v > mx) mx = v;
         if (a < d.K && !(v > 0.0)) ++unused;
     }
-    s_red[tid] = mx;
-    s_cnt[tid] = unused;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) {
-            s_red[tid] = fmax(s_red[tid], s_red[tid + w]);
-            s_cnt[tid] += s_cnt[tid + w];
-        }
-        __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+        unused += __shfl_xor(unused, off, 64);
     }
-    const double maxdiag = s_red[0];
-    if (tid == 0) status[4 * blockIdx.x + 0] = s_cnt[0];
-    __shared__ int s_failed_final;
+    if ((tid & 63) == 0) {
+        s_red[tid >> 6] = mx;
+        s_cnt[tid >> 6] = unused;
+    }
     if (tid == 0) s_failed_final = 0;
     __syncthreads();
+    if (tid == 0) {
+        double a = 0.0;
+        int c = 0;
+        for (int w = 0; w < CT / 64; ++w) {
+            a = fmax(a, s_red[w]);
+            c += s_cnt[w];
+        }
+        s_red[0] = a;
+        status[4 * blockIdx.x + 0] = c;
+    }
+    __syncthreads();
+    const double maxdiag = s_red[0];
 
     for (int attempt = 0; attempt < 2; ++attempt) {
         const double lam = attempt == 0 ? 0.0 : RIDGE * maxdiag;
         // W = P (+ lam I on active atoms, identity on unused ones)
-        const int64_t total = ld * Kp;
-        for (int64_t f = tid; f < total; f += 256) {
-            const int64_t col = f / ld;
-            const int64_t row = f - col * ld;
+        const int ldi = (int)ld;
+        const int total = ldi * Kp;                 // < 2^31: (1024 + 256) * 1024
+#pragma unroll 4
+        for (int f = tid; f < total; f += CT) {
+            const int col = f / ldi;
+            const int row = f - col * ldi;
             double v = P[f];
             if (row == col) v = active[col] ? v + lam : 1.0;
             W[f] = v;
         }
-        for (int a = tid; a < Kp; a += 256) diag0[a] = active[a] ? P[(int64_t)a * ld + a] + lam : 1.0;
+        for (int a = tid; a < Kp; a += CT) diag0[a] = active[a] ? P[(int64_t)a * ld + a] + lam : 1.0;
         if (tid == 0) s_fail = 0;
         __syncthreads();
 
@@ -224,7 +238,6 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(const ModDesc* __restri
                     if (tid > j && tid < NB) Ld[tid][j] /= dj;
                     __builtin_amdgcn_s_waitcnt(0);
                     __builtin_amdgcn_wave_barrier();
-                    // rank-1 update of the trailing part of the block
                     for (int f = tid; f < NB * NB; f += 64) {
                         const int i = f / NB, c = f % NB;
                         if (c > j && i >= c) Ld[i][c] -= Ld[i][j] * Ld[c][j];
@@ -239,46 +252,64 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(const ModDesc* __restri
             }
             __syncthreads();
             if (s_fail) break;
-            // (ii) panel: rows below the block (A rows and the B rows): x L^T = w
-            for (int64_t i = kb + NB + tid; i < ld; i += 256) {
+            // (ii) panel rows below the block (A rows and the B rows): x L^T = w
+            const int64_t r0 = kb + NB;
+            const int R = (int)(ld - r0);
+            const bool in_lds = R + 4 <= PANEL_LDS_ROWS;      // tiles read up to 3 rows past R
+            for (int rr = tid; rr < R; rr += CT) {
+                const int64_t i = r0 + rr;
                 double x[NB];
 #pragma unroll
                 for (int c = 0; c < NB; ++c) x[c] = W[(int64_t)(kb + c) * ld + i];
 #pragma unroll
                 for (int c = 0; c < NB; ++c) {
-                    double s = x[c];
+                    double sacc = x[c];
 #pragma unroll
-                    for (int cc = 0; cc < c; ++cc) s -= x[cc] * Ld[c][cc];
-                    x[c] = s / Ld[c][c];
+                    for (int cc = 0; cc < c; ++cc) sacc -= x[cc] * Ld[c][cc];
+                    x[c] = sacc / Ld[c][c];
+                    __asm__ volatile("" ::: "memory");   // keep the LDS reads of row c here
                 }
 #pragma unroll
                 for (int c = 0; c < NB; ++c) W[(int64_t)(kb + c) * ld + i] = x[c];
+                if (in_lds) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) panel[c * PANEL_LDS_ROWS + rr] = x[c];
+                }
             }
             __syncthreads();
-            // (iii) trailing update: W[i][j] -= sum_c W[i][kb+c] W[j][kb+c], j in [kb+NB, Kp),
-            //       i in [j, ld); 4x4 register tiles over (i, j)
-            const int j0 = kb + NB;
-            const int nj = Kp - j0;
+            // (iii) trailing update W[i][j] -= sum_c X[i][c] X[j][c] for j in [r0, Kp), i in [j, ld):
+            //       4x4 register tiles, row-block fastest across threads (a wave touches 2 KB of a
+            //       column at a time); X from the transposed LDS panel (4 rows of a lane = one
+            //       32-byte read, the j values broadcast) or from global memory
+            const int nj = Kp - (int)r0;
             if (nj > 0) {
-                const int ni = (int)(ld - j0);
-                const int tj = (nj + 3) / 4, ti = (ni + 3) / 4;
-                for (int t = tid; t < tj * ti; t += 256) {
-                    const int bj = t % tj, bi = t / tj;
-                    const int jb = j0 + 4 * bj;
-                    const int ib = j0 + 4 * bi;
-                    if (ib + 3 < jb) continue;       // tile entirely above the diagonal
+                const int tj = (nj + 3) / 4, ti = (R + 3) / 4;
+                for (int t = tid; t < tj * ti; t += CT) {
+                    const int bi = t % ti, bj = t / ti;
+                    const int jl = 4 * bj, il = 4 * bi;       // local (panel) row indices
+                    if (il + 3 < jl) continue;                // tile entirely above the diagonal
                     double acc[4][4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
 #pragma unroll
                         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 2
                     for (int c = 0; c < NB; ++c) {
-                        const double* colc = W + (int64_t)(kb + c) * ld;
                         double xi[4], xj[4];
+                        if (in_lds) {
+                            const double* pc = panel + c * PANEL_LDS_ROWS;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            xi[u] = (ib + u < ld) ? colc[ib + u] : 0.0;
-                            xj[u] = (jb + u < Kp) ? colc[jb + u] : 0.0;
+                            for (int u = 0; u < 4; ++u) {
+                                xi[u] = pc[il + u];     // rows >= R hold finite junk; never stored
+                                xj[u] = pc[jl + u];
+                            }
+                        } else {
+                            const double* colc = W + (int64_t)(kb + c) * ld + r0;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                xi[u] = il + u < R ? colc[il + u] : 0.0;
+                                xj[u] = jl + u < nj ? colc[jl + u] : 0.0;
+                            }
                         }
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
@@ -287,13 +318,13 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(const ModDesc* __restri
                     }
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int j = jb + v;
-                        if (j >= Kp) continue;
+                        const int j = jl + v;
+                        if (j >= nj) continue;
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            const int64_t i = ib + u;
-                            if (i < j || i >= ld) continue;
-                            W[(int64_t)j * ld + i] -= acc[u][v];
+                            const int i = il + u;
+                            if (i < j || i >= R) continue;
+                            W[(r0 + j) * ld + r0 + i] -= acc[u][v];
                         }
                     }
                 }
@@ -310,26 +341,95 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(const ModDesc* __restri
     }
     if (s_failed_final) return;
 
-    // D L = Z for every row r of D (Z = rows Kp .. Kp+m of W); solved in place in W.
-    for (int r = tid; r < m; r += 256) {
-        const int64_t zr = Kp + r;
-        for (int j = Kp - 1; j >= 0; --j) {
-            double s = W[(int64_t)j * ld + zr];
-            for (int i = j + 1; i < Kp; ++i) s -= W[(int64_t)i * ld + zr] * W[(int64_t)j * ld + i];
-            W[(int64_t)j * ld + zr] = s / W[(int64_t)j * ld + j];
+    // D L = Z (Z = rows Kp .. Kp+m of W, D overwrites Z): blocks of NB columns from the right.
+    // Z[:, blk] -= D[:, right] L[right, blk] accumulated over 64-row chunks of D and L staged in
+    // LDS by all threads (every thread owns outputs (r, c); a wave shares c), then the small
+    // triangle D[:, blk] L[blk, blk] = Z[:, blk] row by row with L[blk, blk] in LDS.
+    {
+        // chunk rows so that D (CH x m) and L (CH x NB) fit in the panel buffer
+        const int CH = 64 * (m + NB) <= PANEL_LDS_ROWS * NB ? 64 : 32;
+        double* Dc = panel;                    // CH x m   (D[r][i0 + i] at Dc[i * m + r])
+        double* Lc = panel + CH * m;           // CH x NB
+        const int n_out = m * NB;
+        constexpr int OPT = (SMDL_MAX_M * NB + CT - 1) / CT;   // outputs per thread (max)
+        for (int jb = Kp - NB; jb >= 0; jb -= NB) {
+            const int je = jb + NB;
+            double acc[OPT];
+#pragma unroll
+            for (int q = 0; q < OPT; ++q) acc[q] = 0.0;
+            for (int i0 = je; i0 < Kp; i0 += CH) {
+                const int nr = Kp - i0 < CH ? Kp - i0 : CH;
+                for (int f = tid; f < nr * m; f += CT) {
+                    const int i = f / m, r = f - i * m;
+                    Dc[i * m + r] = W[(int64_t)(i0 + i) * ld + Kp + r];
+                }
+                for (int f = tid; f < nr * NB; f += CT) {
+                    const int c = f / nr, i = f - c * nr;
+                    Lc[i * NB + c] = W[(int64_t)(jb + c) * ld + i0 + i];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < OPT; ++q) {
+                    const int o = tid + q * CT;
+                    if (o < n_out) {
+                        const int r = o % m, c = o / m;
+                        double s0 = 0.0, s1 = 0.0;
+                        int i = 0;
+                        for (; i + 2 <= nr; i += 2) {
+                            s0 += Dc[i * m + r] * Lc[i * NB + c];
+                            s1 += Dc[(i + 1) * m + r] * Lc[(i + 1) * NB + c];
+                        }
+                        if (i < nr) s0 += Dc[i * m + r] * Lc[i * NB + c];
+                        acc[q] += s0 + s1;
+                    }
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int q = 0; q < OPT; ++q) {
+                const int o = tid + q * CT;
+                if (o < n_out) {
+                    const int r = o % m, c = o / m;
+                    W[(int64_t)(jb + c) * ld + Kp + r] -= acc[q];
+                }
+            }
+            for (int f = tid; f < NB * NB; f += CT) {
+                const int i = f / NB, j = f % NB;
+                Ld[i][j] = i >= j ? W[(int64_t)(jb + j) * ld + jb + i] : 0.0;
+            }
+            __syncthreads();
+            for (int r = tid; r < m; r += CT) {
+                const int64_t zr = Kp + r;
+                double x[NB];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) x[c] = W[(int64_t)(jb + c) * ld + zr];
+#pragma unroll
+                for (int c = NB - 1; c >= 0; --c) {
+                    double sacc = x[c];
+#pragma unroll
+                    for (int i = c + 1; i < NB; ++i) sacc -= x[i] * Ld[i][c];
+                    x[c] = sacc / Ld[c][c];
+                    __asm__ volatile("" ::: "memory");
+                }
+#pragma unroll
+                for (int c = 0; c < NB; ++c) W[(int64_t)(jb + c) * ld + zr] = x[c];
+            }
+            __syncthreads();
         }
     }
-    __syncthreads();
-    // normalise and store the active atoms
-    for (int j = tid; j < d.K; j += 256) {
+    // normalise and store the active atoms (one wave per atom)
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int j = wv; j < d.K; j += CT / 64) {
         if (!active[j]) continue;
         double ss = 0.0;
-        for (int r = 0; r < m; ++r) {
+        for (int r = lane; r < m; r += 64) {
             const double v = W[(int64_t)j * ld + Kp + r];
             ss += v * v;
         }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
         const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 1.0;
-        for (int r = 0; r < m; ++r) d.D[(int64_t)j * m + r] = (float)(W[(int64_t)j * ld + Kp + r] * inv);
+        for (int r = lane; r < m; r += 64) d.D[(int64_t)j * m + r] = (float)(W[(int64_t)j * ld + Kp + r] * inv);
     }
 }
 
@@ -360,6 +460,6 @@ hipError_t launch_mod(const ModDesc* dev_desc, const ModDesc* host_desc, int n_d
     hipLaunchKernelGGL(mod_products_kernel, dim3(max_kpad, n_desc), dim3(256), 0, st, dev_desc, m, ptr,
                        list_sig, list_coef);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(n_desc), dim3(256), 0, st, dev_desc, m, status);
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status);
     return hipGetLastError();
 }

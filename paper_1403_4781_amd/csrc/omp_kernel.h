@@ -38,6 +38,39 @@ __device__ __forceinline__ float f4get(const float4& v, int e) {
     return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
 }
 
+
+// (value, index) combine of the argmax: larger |value| wins, the lower index on equal |value|.
+// The order is total, so any reduction tree gives the same winner.
+__device__ __forceinline__ void argmax_combine(float& bv, int& bi, float ov, int oi) {
+    const bool take = fabsf(ov) > fabsf(bv) || (fabsf(ov) == fabsf(bv) && oi < bi);
+    bv = take ? ov : bv;
+    bi = take ? oi : bi;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void dpp_combine(float& bv, int& bi) {
+    const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bv), CTRL, 0xf, 0xf, false));
+    const int oi = __builtin_amdgcn_mov_dpp(bi, CTRL, 0xf, 0xf, false);
+    argmax_combine(bv, bi, ov, oi);
+}
+
+// All-reduce of the argmax over the G lanes of a signal group (G = 16, 32 or 64; groups are
+// aligned).  Within a row of 16 lanes: DPP quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror and row_mirror (VALU latency); across rows: lane shuffles.
+template <int G>
+__device__ __forceinline__ void group_argmax(float& bv, int& bi) {
+    dpp_combine<0xB1>(bv, bi);    // quad_perm [1,0,3,2]
+    dpp_combine<0x4E>(bv, bi);    // quad_perm [2,3,0,1]
+    dpp_combine<0x141>(bv, bi);   // row_half_mirror: quad q <-> quad 1-q within 8 lanes
+    dpp_combine<0x140>(bv, bi);   // row_mirror: half h <-> half 1-h within 16 lanes
+#pragma unroll
+    for (int off = 16; off < G; off <<= 1) {
+        const float ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        argmax_combine(bv, bi, ov, oi);
+    }
+}
+
 template <int EM, int SM>
 struct State {
     float c[EM];
@@ -74,14 +107,7 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
             if (fabsf(st.c[t]) > fabsf(bv)) { bv = st.c[t]; bi = e; }
         }
     }
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        const float ov = __shfl_xor(bv, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        const bool take = fabsf(ov) > fabsf(bv) || (fabsf(ov) == fabsf(bv) && oi < bi);
-        bv = take ? ov : bv;
-        bi = take ? oi : bi;
-    }
+    group_argmax<G>(bv, bi);
     const int j = bi;
     const float cj = bv;
     if (!(fabsf(cj) > x.tau * x.ynrm)) st.live = false;

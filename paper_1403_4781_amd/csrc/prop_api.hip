@@ -43,6 +43,8 @@ struct Acts {
     std::vector<uint16_t*> dB;     // deltas BF16
     double* loss_part = nullptr;
     double* loss = nullptr;
+    uint16_t* tB = nullptr;        // transposed delta (widths x Bpad)
+    uint16_t* tH = nullptr;        // transposed activation (widths x Bpad)
 };
 
 smdl_status get_acts(smdl_t h, smdl_prop_t p, int64_t Bpad, bool train, Acts& a) {
@@ -64,6 +66,11 @@ smdl_status get_acts(smdl_t h, smdl_prop_t p, int64_t Bpad, bool train, Acts& a)
             a.dB[l] = (uint16_t*)h->ws(nb.c_str(), (size_t)Bpad * p->widths[l + 1] * 2);
             if (!a.dF[l] || !a.dB[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
         }
+        int wmax = 0;
+        for (int w : p->widths) wmax = std::max(wmax, w);
+        a.tB = (uint16_t*)h->ws("prop.tB", (size_t)Bpad * wmax * 2);
+        a.tH = (uint16_t*)h->ws("prop.tH", (size_t)Bpad * wmax * 2);
+        if (!a.tB || !a.tH) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
         a.loss_part = (double*)h->ws("prop.lossp", (size_t)Bpad * 8);
         a.loss = (double*)h->ws("prop.loss", 8);
         if (!a.loss_part || !a.loss) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
@@ -113,32 +120,40 @@ hipError_t enqueue_grad(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, cons
                    a.dF[L - 1], a.dB[L - 1], a.loss_part, a.loss, h->stream);
     if (e != hipSuccess) return e;
     for (int l = L - 1; l >= 0; --l) {
-        // dW_l = delta_l^T h_l   (M = out, N = in, K = Bpad), both operands stored transposed
+        // dW_l = delta_l^T h_l (M = out, N = in, K = Bpad): both operands transposed once through
+        // LDS, then the row-major GEMM with the batch split over blockIdx.z
+        const int wo = p->widths[l + 1], wi = p->widths[l];
+        if ((e = launch_transpose_bf16(a.dB[l], (int)Bpad, wo, a.tB, h->stream)) != hipSuccess) return e;
+        if ((e = launch_transpose_bf16(a.h[l], (int)Bpad, wi, a.tH, h->stream)) != hipSuccess) return e;
+        if ((e = launch_zero_f32(dW[l], (int64_t)wo * wi, h->stream)) != hipSuccess) return e;
         GemmArgs g{};
-        g.A = a.dB[l];
-        g.lda = p->widths[l + 1];
-        g.B = a.h[l];
-        g.ldb = p->widths[l];
-        g.M = p->widths[l + 1];
-        g.N = p->widths[l];
+        g.A = a.tB;
+        g.lda = (int)Bpad;
+        g.B = a.tH;
+        g.ldb = (int)Bpad;
+        g.M = wo;
+        g.N = wi;
         g.K = (int)Bpad;
-        g.ldc = p->widths[l];
+        g.ldc = wi;
         g.out_f32 = dW[l];
-        if ((e = launch_gemm(g, true, true, false, h->stream)) != hipSuccess) return e;
-        if ((e = launch_colsum(a.dF[l], Bpad, p->widths[l + 1], db[l], h->stream)) != hipSuccess) return e;
+        g.ksplit = 1;
+        const int tiles = ((wo + 63) / 64) * ((wi + 63) / 64);
+        while (g.ksplit < 8 && tiles * g.ksplit * 2 <= 512 && Bpad % (32 * g.ksplit * 2) == 0) g.ksplit *= 2;
+        if ((e = launch_gemm(g, false, false, false, h->stream)) != hipSuccess) return e;
+        if ((e = launch_colsum(a.dF[l], Bpad, wo, db[l], h->stream)) != hipSuccess) return e;
         if (l > 0) {
             // delta_{l-1} = (delta_l W_l) * [h_l > 0]   (M = Bpad, N = in, K = out)
             GemmArgs q{};
             q.A = a.dB[l];
-            q.lda = p->widths[l + 1];
+            q.lda = wo;
             q.B = p->WbfT[l];
-            q.ldb = p->widths[l + 1];
+            q.ldb = wo;
             q.M = (int)Bpad;
-            q.N = p->widths[l];
-            q.K = p->widths[l + 1];
-            q.ldc = p->widths[l];
+            q.N = wi;
+            q.K = wo;
+            q.ldc = wi;
             q.mask_bf16 = a.h[l];
-            q.ldmask = p->widths[l];
+            q.ldmask = wi;
             q.out_f32 = a.dF[l - 1];
             q.out_bf16 = a.dB[l - 1];
             if ((e = launch_gemm(q, false, false, false, h->stream)) != hipSuccess) return e;

@@ -1,13 +1,15 @@
 // Candidate selection and proposer-restricted OMP.
 //
-// topk: one wave per signal; n_cand rounds of a wave argmax over the logits (larger logit
+// topk: 16 lanes per signal; n_cand rounds of a group argmax over the logits (larger logit
 //   first, lower atom index on equal logits); the chosen atoms are written in increasing atom
-//   order (ballot prefix counts).
+//   order.
 // restricted_omp: one group of 16 lanes per signal.  OMP on the candidate columns only:
 //   alpha_C = D_C^T y by gathered dot products, the same correlation-space progressive
 //   inverse-Cholesky steps as the full kernel with rows of G gathered at the candidates, then
 //   the explicit FP32 residual r = y - D_I x_I.  ||r|| > eps_fb marks the signal for the full
 //   OMP fallback (appended to a device list, no host round trip).
+#include <utility>
+
 #include "mlp_internal.h"
 
 namespace {
@@ -16,53 +18,185 @@ constexpr int MAXC = 64;        // candidates per signal
 constexpr int GR = 16;          // lanes per signal
 constexpr int EC = MAXC / GR;   // candidate entries per lane
 
+// Top-n_cand selection: 16 lanes per signal (4 signals per wave).  Lane g holds the logits
+// of atoms g, g+16, ... (up to 64 of them for K <= 1024); every round takes the best head over
+// the 16 lanes (DPP butterfly inside the row: larger logit, lower atom on ties) and the owner
+// advances past it.  The chosen atoms are then written in increasing atom order.
+__device__ __forceinline__ void tk_combine(float& bv, int& bi, float ov, int oi) {
+    const bool take = ov > bv || (ov == bv && oi < bi);
+    bv = take ? ov : bv;
+    bi = take ? oi : bi;
+}
+template <int CTRL>
+__device__ __forceinline__ void tk_dpp(float& bv, int& bi) {
+    const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bv), CTRL, 0xf, 0xf, false));
+    const int oi = __builtin_amdgcn_mov_dpp(bi, CTRL, 0xf, 0xf, false);
+    tk_combine(bv, bi, ov, oi);
+}
+
+constexpr int TKE = SMDL_MAX_K / 16;   // logits per lane
+
+// (|value| larger, then lower candidate position) combine for the restricted argmax.
+template <int CTRL>
+__device__ __forceinline__ void ro_dpp(float& bv, int& bp) {
+    const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bv), CTRL, 0xf, 0xf, false));
+    const int op = __builtin_amdgcn_mov_dpp(bp, CTRL, 0xf, 0xf, false);
+    const bool take = fabsf(ov) > fabsf(bv) || (fabsf(ov) == fabsf(bv) && op < bp);
+    bv = take ? ov : bv;
+    bp = take ? op : bp;
+}
+
 __global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ logits, int64_t N, int K,
                                                    int n_cand, int32_t* __restrict__ cand) {
+    __shared__ unsigned int chosen[16][SMDL_MAX_K / 32];
     const int lane = threadIdx.x & 63;
-    const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (n >= N) return;
-    constexpr int EK = SMDL_MAX_K / 64;
-    float v[EK];
-    bool taken[EK];
-    const int E = (K + 63) / 64;
+    const int g = lane & 15;
+    const int slot = threadIdx.x >> 4;
+    const int64_t n = (int64_t)blockIdx.x * 16 + slot;
+    const bool valid = n < N;
+    for (int w = g; w < SMDL_MAX_K / 32; w += 16) chosen[slot][w] = 0u;
+    const int E = (K + 15) / 16;
+    float v[TKE];
+    bool used[TKE];
 #pragma unroll
-    for (int t = 0; t < EK; ++t) {
-        const int k = lane + 64 * t;
-        v[t] = (t < E && k < K) ? logits[n * K + k] : -INFINITY;
-        if (v[t] != v[t]) v[t] = -INFINITY;     // NaN logits rank last
-        taken[t] = !(t < E && k < K);
+    for (int t = 0; t < TKE; ++t) {
+        const int k = g + 16 * t;
+        const bool ok = valid && t < E && k < K;
+        float x = ok ? logits[n * K + k] : -INFINITY;
+        if (x != x) x = -INFINITY;          // NaN logits rank last
+        v[t] = x;
+        used[t] = !ok;
     }
+    __syncthreads();
     for (int c = 0; c < n_cand; ++c) {
+        // this lane's best unused entry
         float bv = -INFINITY;
         int bi = 0x7fffffff;
 #pragma unroll
-        for (int t = 0; t < EK; ++t) {
-            const int k = lane + 64 * t;
-            if (!taken[t] && (v[t] > bv || (v[t] == bv && k < bi))) { bv = v[t]; bi = k; }
+        for (int t = 0; t < TKE; ++t) {
+            const int k = g + 16 * t;
+            if (t < E && !used[t] && (v[t] > bv || (v[t] == bv && k < bi))) { bv = v[t]; bi = k; }
         }
+        tk_dpp<0xB1>(bv, bi);
+        tk_dpp<0x4E>(bv, bi);
+        tk_dpp<0x141>(bv, bi);
+        tk_dpp<0x140>(bv, bi);
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float ov = __shfl_xor(bv, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
-#pragma unroll
-        for (int t = 0; t < EK; ++t)
-            if (lane + 64 * t == bi) taken[t] = true;
+        for (int t = 0; t < TKE; ++t)
+            if (g + 16 * t == bi) used[t] = true;
+        if (g == 0 && valid && bi < K) chosen[slot][bi >> 5] |= 1u << (bi & 31);
     }
-    // chosen = taken minus the padding; write in increasing atom order
-    int base = 0;
-#pragma unroll
-    for (int t = 0; t < EK; ++t) {
-        const int k = lane + 64 * t;
-        const bool chosen = taken[t] && t < E && k < K;
-        const unsigned long long mask = __ballot(chosen);
-        const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-        if (chosen && pos < n_cand) cand[n * n_cand + pos] = k;
-        base += __popcll(mask);
+    __syncthreads();
+    if (!valid) return;
+    // increasing atom order: prefix counts over the bitmask words
+    if (g == 0) {
+        int pos = 0;
+        for (int w = 0; w < (K + 31) / 32 && pos < n_cand; ++w) {
+            unsigned int bits = chosen[slot][w];
+            while (bits && pos < n_cand) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                cand[n * n_cand + pos++] = 32 * w + b;
+            }
+        }
     }
 }
 
+template <int SM>
+struct RState {
+    float c[EC];
+    float U[SM][EC];
+    float Linv[SM][SM];
+    float pi[SM];
+    int sel[SM];
+    int k;
+    bool live;
+};
+
+struct RCtx {
+    const RestrictedArgs* a;
+    const int* cid;
+    int64_t n;
+    int g;
+    float ynrm;
+};
+
+// One greedy step over the candidates (KK is a compile-time constant so that every register
+// array index is static).  Returns false when the whole wave is done.
+template <int KK, int SM>
+__device__ __forceinline__ bool r_step(RState<SM>& st, const RCtx& x) {
+    const RestrictedArgs& a = *x.a;
+    if (KK >= a.s) return false;
+    if (!__any(st.live)) return false;
+    // argmax over candidates: position order = atom order, so the lower position wins ties
+    float bv = 0.f;
+    int bp = 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < EC; ++t) {
+        const int e = x.g + GR * t;
+        if (x.cid[t] >= 0 && (fabsf(st.c[t]) > fabsf(bv) || (fabsf(st.c[t]) == fabsf(bv) && e < bp))) {
+            bv = st.c[t];
+            bp = e;
+        }
+    }
+    ro_dpp<0xB1>(bv, bp);
+    ro_dpp<0x4E>(bv, bp);
+    ro_dpp<0x141>(bv, bp);
+    ro_dpp<0x140>(bv, bp);
+    if (!(fabsf(bv) > a.tau * x.ynrm) || bp >= a.n_cand) st.live = false;
+    if (st.live) {
+        const int j = a.cand[x.n * a.n_cand + bp];
+        const float* grow = a.gram + (int64_t)j * a.Kpad;
+        float gs[KK > 0 ? KK : 1];
+#pragma unroll
+        for (int i = 0; i < KK; ++i) gs[i] = grow[st.sel[i]];
+        const float gjj = grow[j];
+        float w[KK > 0 ? KK : 1];
+        float l2 = gjj;
+#pragma unroll
+        for (int i = 0; i < KK; ++i) {
+            float acc = 0.f;
+#pragma unroll
+            for (int l = 0; l <= i; ++l) acc = fmaf(st.Linv[i][l], gs[l], acc);
+            w[i] = acc;
+            l2 = fmaf(-acc, acc, l2);
+        }
+        if (!(l2 > a.dep_tol * gjj)) {
+            st.live = false;
+        } else {
+            const float rl = 1.0f / sqrtf(l2);
+#pragma unroll
+            for (int l = 0; l < KK; ++l) {
+                float acc = 0.f;
+#pragma unroll
+                for (int i = l; i < KK; ++i) acc = fmaf(w[i], st.Linv[i][l], acc);
+                st.Linv[KK][l] = -acc * rl;
+            }
+            st.Linv[KK][KK] = rl;
+            const float pk = bv * rl;
+#pragma unroll
+            for (int t = 0; t < EC; ++t) {
+                float u = x.cid[t] >= 0 ? grow[x.cid[t]] : 0.f;
+#pragma unroll
+                for (int i = 0; i < KK; ++i) u = fmaf(-st.U[i][t], w[i], u);
+                u *= rl;
+                st.U[KK][t] = u;
+                st.c[t] = fmaf(-pk, u, st.c[t]);
+            }
+            st.pi[KK] = pk;
+            st.sel[KK] = j;
+            st.k = KK + 1;
+        }
+    }
+    return true;
+}
+
+template <int SM, int... KKs>
+__device__ __forceinline__ void r_run(RState<SM>& st, const RCtx& x, std::integer_sequence<int, KKs...>) {
+    (void)(r_step<KKs, SM>(st, x) && ...);
+}
+
+template <int SM>
 __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
     __shared__ float ys[16][SMDL_MAX_M];
     const int tid = threadIdx.x;
@@ -73,15 +207,15 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
     const bool valid = n < a.N;
     const int m = a.m;
     const int nc = a.n_cand;
-    // stage y
     for (int i = g; i < m; i += GR) ys[slot][i] = valid ? a.Y[n * m + i] : 0.f;
     __syncthreads();
     int cid[EC];
-    float c[EC];
+    RState<SM> st;
     float ysq = 0.f;
     for (int i = g; i < m; i += GR) ysq = fmaf(ys[slot][i], ys[slot][i], ysq);
 #pragma unroll
     for (int off = 1; off < GR; off <<= 1) ysq += __shfl_xor(ysq, off, 64);
+    const bool vec = (m & 3) == 0 && (reinterpret_cast<uintptr_t>(a.D) & 15) == 0;
 #pragma unroll
     for (int t = 0; t < EC; ++t) {
         const int e = g + GR * t;
@@ -90,106 +224,48 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
         float acc = 0.f;
         if (cid[t] >= 0) {
             const float* d = a.D + (int64_t)cid[t] * m;
-            for (int i = 0; i < m; ++i) acc = fmaf(d[i], ys[slot][i], acc);
-        }
-        c[t] = acc;
-    }
-    const float ynrm = sqrtf(ysq);
-    float U[SMDL_MAX_S][EC];
-    float Linv[SMDL_MAX_S][SMDL_MAX_S];
-    float pi[SMDL_MAX_S];
-    int sel[SMDL_MAX_S];
-#pragma unroll
-    for (int i = 0; i < SMDL_MAX_S; ++i) {
-        pi[i] = 0.f;
-        sel[i] = 0;
-#pragma unroll
-        for (int l = 0; l <= i; ++l) Linv[i][l] = 0.f;
-    }
-    bool live = valid;
-    int k = 0;
-#pragma unroll
-    for (int kk = 0; kk < SMDL_MAX_S; ++kk) {
-        if (kk >= a.s) break;
-        if (!__any(live)) break;
-        // argmax over candidates: position order = atom order, so lower position wins ties
-        float bv = 0.f;
-        int bp = 0x7fffffff;
-#pragma unroll
-        for (int t = 0; t < EC; ++t) {
-            const int e = g + GR * t;
-            if (cid[t] >= 0 && (fabsf(c[t]) > fabsf(bv) || (fabsf(c[t]) == fabsf(bv) && e < bp))) {
-                bv = c[t];
-                bp = e;
-            }
-        }
-#pragma unroll
-        for (int off = 1; off < GR; off <<= 1) {
-            const float ov = __shfl_xor(bv, off, 64);
-            const int op = __shfl_xor(bp, off, 64);
-            if (fabsf(ov) > fabsf(bv) || (fabsf(ov) == fabsf(bv) && op < bp)) { bv = ov; bp = op; }
-        }
-        if (!(fabsf(bv) > a.tau * ynrm) || bp >= nc) live = false;
-        if (live) {
-            const int j = a.cand[n * nc + bp];
-            const float* grow = a.gram + (int64_t)j * a.Kpad;
-            float gs[SMDL_MAX_S];
-#pragma unroll
-            for (int i = 0; i < kk; ++i) gs[i] = grow[sel[i]];
-            const float gjj = grow[j];
-            float w[SMDL_MAX_S];
-            float l2 = gjj;
-#pragma unroll
-            for (int i = 0; i < kk; ++i) {
-                float acc = 0.f;
-#pragma unroll
-                for (int l = 0; l <= i; ++l) acc = fmaf(Linv[i][l], gs[l], acc);
-                w[i] = acc;
-                l2 = fmaf(-acc, acc, l2);
-            }
-            if (!(l2 > a.dep_tol * gjj)) {
-                live = false;
-            } else {
-                const float rl = 1.0f / sqrtf(l2);
-#pragma unroll
-                for (int l = 0; l < kk; ++l) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int i = l; i < kk; ++i) acc = fmaf(w[i], Linv[i][l], acc);
-                    Linv[kk][l] = -acc * rl;
+            int i = 0;
+            if (vec) {
+                for (; i < m; i += 4) {
+                    const float4 dv = *reinterpret_cast<const float4*>(d + i);
+                    const float4 yv = *reinterpret_cast<const float4*>(&ys[slot][i]);
+                    acc = fmaf(dv.x, yv.x, acc);
+                    acc = fmaf(dv.y, yv.y, acc);
+                    acc = fmaf(dv.z, yv.z, acc);
+                    acc = fmaf(dv.w, yv.w, acc);
                 }
-                Linv[kk][kk] = rl;
-                const float pk = bv * rl;
-#pragma unroll
-                for (int t = 0; t < EC; ++t) {
-                    float u = cid[t] >= 0 ? grow[cid[t]] : 0.f;
-#pragma unroll
-                    for (int i = 0; i < kk; ++i) u = fmaf(-U[i][t], w[i], u);
-                    u *= rl;
-                    U[kk][t] = u;
-                    c[t] = fmaf(-pk, u, c[t]);
-                }
-                pi[kk] = pk;
-                sel[kk] = j;
-                k = kk + 1;
             }
+            for (; i < m; ++i) acc = fmaf(d[i], ys[slot][i], acc);
         }
+        st.c[t] = acc;
     }
+#pragma unroll
+    for (int i = 0; i < SM; ++i) {
+        st.pi[i] = 0.f;
+        st.sel[i] = 0;
+#pragma unroll
+        for (int l = 0; l <= i; ++l) st.Linv[i][l] = 0.f;
+    }
+    st.live = valid;
+    st.k = 0;
+    RCtx x{&a, cid, n, g, sqrtf(ysq)};
+    r_run<SM>(st, x, std::make_integer_sequence<int, SM>{});
+    const int k = st.k;
     // coefficients and the explicit residual
-    float gam[SMDL_MAX_S];
+    float gam[SM];
 #pragma unroll
-    for (int l = 0; l < SMDL_MAX_S; ++l) {
+    for (int l = 0; l < SM; ++l) {
         float acc = 0.f;
 #pragma unroll
-        for (int i = l; i < SMDL_MAX_S; ++i) acc = fmaf(Linv[i][l], (i < k) ? pi[i] : 0.f, acc);
+        for (int i = l; i < SM; ++i) acc = fmaf(st.Linv[i][l], (i < k) ? st.pi[i] : 0.f, acc);
         gam[l] = acc;
     }
     float rr = 0.f;
     for (int i = g; i < m; i += GR) {
         float r = ys[slot][i];
 #pragma unroll
-        for (int l = 0; l < SMDL_MAX_S; ++l)
-            if (l < k) r = fmaf(-gam[l], a.D[(int64_t)sel[l] * m + i], r);
+        for (int l = 0; l < SM; ++l)
+            if (l < k) r = fmaf(-gam[l], a.D[(int64_t)st.sel[l] * m + i], r);
         rr = fmaf(r, r, rr);
     }
 #pragma unroll
@@ -208,8 +284,8 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
         int oi = -1;
         float oc = 0.f;
 #pragma unroll
-        for (int i = 0; i < SMDL_MAX_S; ++i)
-            if (i == g && i < k) { oi = sel[i]; oc = gam[i]; }
+        for (int i = 0; i < SM; ++i)
+            if (i == g && i < k) { oi = st.sel[i]; oc = gam[i]; }
         a.idx[n * a.s_out + g] = oi;
         a.coef[n * a.s_out + g] = oc;
     }
@@ -219,11 +295,14 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
 }  // namespace
 
 hipError_t launch_topk(const float* logits, int64_t N, int K, int n_cand, int32_t* cand, hipStream_t st) {
-    hipLaunchKernelGGL(topk_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, logits, N, K, n_cand, cand);
+    hipLaunchKernelGGL(topk_kernel, dim3((unsigned)((N + 15) / 16)), dim3(256), 0, st, logits, N, K, n_cand, cand);
     return hipGetLastError();
 }
 
 hipError_t launch_restricted_omp(const RestrictedArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(restricted_omp_kernel, dim3((unsigned)((a.N + 15) / 16)), dim3(256), 0, st, a);
+    if (a.s <= 8)
+        hipLaunchKernelGGL(restricted_omp_kernel<8>, dim3((unsigned)((a.N + 15) / 16)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(restricted_omp_kernel<SMDL_MAX_S>, dim3((unsigned)((a.N + 15) / 16)), dim3(256), 0, st, a);
     return hipGetLastError();
 }

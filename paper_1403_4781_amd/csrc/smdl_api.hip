@@ -328,6 +328,12 @@ smdl_status omp_code_impl(smdl_t h, const float* D, int m, int K, const float* Y
     CodePlan plan;
     smdl_status st;
     if ((st = prepare_sets(h, m, sets, tag, plan)) != SMDL_OK) return st;
+    if (h->autotune && !sig_list && N >= 4096) {
+        // first call of this shape: time the candidate tiles on this data (codes are rewritten below)
+        CodeOut tout{X.idx, X.coef, X.nnz, nullptr, X.s_max};
+        plan.persistent = false;
+        if ((st = autotune_plan(h, plan, sets, tout, false, tag)) != SMDL_OK) return st;
+    }
     const OmpTile tile = choose_tile(h, plan.maxKpad, s_max, false);
     const int T = 16 * tile.tt;
     hipError_t e;
