@@ -6,15 +6,15 @@
 //  2. mod_products: one block per atom a: column a of A = X X^T (FP64, LDS) and column a of
 //     B = Y X^T (FP64 register accumulation over the atom's list), written below each other as
 //     column a of the augmented matrix M = [A; B] ((Kpad + m) x Kpad, FP64).
-//  3. chol_solve: one block per dictionary: right-looking blocked Cholesky of A that carries the
-//     B rows along (they become Z = B L^-T), then D L = Z by back substitution per row, a ridge
-//     retry when a pivot is rejected, and unit normalisation of the solved atoms.  Atoms no
-//     signal uses get an identity diagonal (their column of A is zero) and keep their value.
+//  3. chol_factor: one block per dictionary: blocked FP64 Cholesky of A (MFMA trailing updates),
+//     a ridge retry when a pivot is rejected.  Atoms no signal uses get an identity diagonal
+//     (their column of A is zero) and keep their value.
+//  4. tri_solve: D A = B row by row (forward then backward substitution), many blocks per
+//     dictionary; mod_normalize: unit normalisation of the solved atoms.
 #include "smdl_internal.h"
 
 namespace {
 
-constexpr int NB = 16;          // Cholesky panel width
 constexpr double PIV_TOL = 1e-12;
 constexpr double RIDGE = 1e-10;
 
@@ -29,7 +29,7 @@ __device__ __forceinline__ int desc_of(const int64_t* __restrict__ starts, int n
 
 // grid.y = descriptor; threads stride over that descriptor's signals.
 // Entries with an atom index outside [0, K) or a count outside [0, s_stride] are skipped
-// everywhere and flagged in status[4*t + 3] (the host turns that into SMDL_E_ARG).
+// everywhere and flagged in status[8*t + 3] (the host turns that into SMDL_E_ARG).
 __device__ __forceinline__ int clamp_nnz(int k, int s) { return k < 0 ? 0 : (k > s ? s : k); }
 
 __global__ void csc_count_kernel(const ModDesc* __restrict__ md, int32_t* __restrict__ cnt,
@@ -45,7 +45,7 @@ __global__ void csc_count_kernel(const ModDesc* __restrict__ md, int32_t* __rest
             if (ix < 0 || ix >= d.K) { bad = true; continue; }
             atomicAdd(&cnt[d.atom0 + ix], 1);
         }
-        if (bad) atomicOr(&status[4 * blockIdx.y + 3], 1);
+        if (bad) atomicOr(&status[8 * blockIdx.y + 3], 1);
     }
 }
 
@@ -147,29 +147,51 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
     }
 }
 
-// One block (512 threads) per dictionary.
-// status[4*t + 0] = unused atoms (this call), [1] |= ridge used, [2] |= failed; the caller zeroes
+// ------------------------------------------------------------------------------------------
+// FP64 Cholesky factorisation of A (one block per dictionary)
+// ------------------------------------------------------------------------------------------
+// status[8*t + 0] = unused atoms (this call), [1] |= ridge used, [2] |= failed, [3] |= bad codes,
+// [4] = failed in this call (read by the solve and normalisation kernels).  The caller zeroes
 // the status array before a sequence of updates.
-constexpr int CT = 512;                       // threads of the solve
-constexpr int PANEL_LDS_ROWS = 896;           // panel rows kept in LDS (896 x 16 doubles = 112 KB)
+//
+// Right-looking, panel width FB = 32:
+//   (i)   the 32 x 32 diagonal block is factored by one wave with one row per lane in registers,
+//         column values broadcast with readlane;
+//   (ii)  the rows below it are solved against it (one row per thread, L_kk in LDS);
+//   (iii) the trailing lower triangle is updated on the FP64 matrix cores (16 x 16 tiles,
+//         v_mfma_f64_16x16x4f64), the panel read from LDS when it fits.
+// Finally L is mirrored into the upper triangle (W[i*ld + j] = L[i][j]) so that the backward
+// substitution reads rows of L contiguously.
+constexpr int FB = 32;
+constexpr int CT = 512;
+constexpr int PR = 480;                      // panel rows kept in LDS (32 x 480 doubles = 120 KB)
 
-__global__ __launch_bounds__(CT) void chol_solve_kernel(const ModDesc* __restrict__ md, int m,
-                                                        int32_t* __restrict__ status) {
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__global__ __launch_bounds__(CT) void chol_factor_kernel(const ModDesc* __restrict__ md, int m,
+                                                         int32_t* __restrict__ status) {
     const ModDesc d = md[blockIdx.x];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int Kp = d.Kpad;
-    const int64_t ld = Kp + m;          // rows of M = [A; B]
-    const double* P = d.A;              // pristine products
-    double* W = d.W;                    // factorisation workspace
-    __shared__ double Ld[NB][NB + 1];
-    __shared__ double panel[PANEL_LDS_ROWS * NB];
+    const int ld = Kp + m;
+    const double* P = d.A;
+    double* W = d.W;
+    __shared__ double Ld[FB][FB + 1];
+    __shared__ double panel[FB * PR];        // panel[c * PR + row]
     __shared__ double diag0[SMDL_MAX_K];
     __shared__ unsigned char active[SMDL_MAX_K];
     __shared__ int s_fail, s_failed_final;
     __shared__ double s_red[CT / 64];
     __shared__ int s_cnt[CT / 64];
+    int32_t* st = status + 8 * blockIdx.x;
 
-    // max active diagonal and unused count
     double mx = 0.0;
     int unused = 0;
     for (int a = tid; a < Kp; a += CT) {
@@ -183,9 +205,9 @@ __global__ __launch_bounds__(CT) void chol_solve_kernel(const ModDesc* __restric
         mx = fmax(mx, __shfl_xor(mx, off, 64));
         unused += __shfl_xor(unused, off, 64);
     }
-    if ((tid & 63) == 0) {
-        s_red[tid >> 6] = mx;
-        s_cnt[tid >> 6] = unused;
+    if (lane == 0) {
+        s_red[wave] = mx;
+        s_cnt[wave] = unused;
     }
     if (tid == 0) s_failed_final = 0;
     __syncthreads();
@@ -197,240 +219,233 @@ __global__ __launch_bounds__(CT) void chol_solve_kernel(const ModDesc* __restric
             c += s_cnt[w];
         }
         s_red[0] = a;
-        status[4 * blockIdx.x + 0] = c;
+        st[0] = c;
+        st[4] = 0;
     }
     __syncthreads();
     const double maxdiag = s_red[0];
 
     for (int attempt = 0; attempt < 2; ++attempt) {
         const double lam = attempt == 0 ? 0.0 : RIDGE * maxdiag;
-        // W = P (+ lam I on active atoms, identity on unused ones)
-        const int ldi = (int)ld;
-        const int total = ldi * Kp;                 // < 2^31: (1024 + 256) * 1024
+        // W[0:Kp, 0:Kp] = A (+ lam I on active atoms, identity on unused ones)
+        const int total = Kp * Kp;
 #pragma unroll 4
         for (int f = tid; f < total; f += CT) {
-            const int col = f / ldi;
-            const int row = f - col * ldi;
-            double v = P[f];
+            const int col = f / Kp, row = f - col * Kp;
+            double v = P[(int64_t)col * ld + row];
             if (row == col) v = active[col] ? v + lam : 1.0;
-            W[f] = v;
+            W[(int64_t)col * ld + row] = v;
         }
         for (int a = tid; a < Kp; a += CT) diag0[a] = active[a] ? P[(int64_t)a * ld + a] + lam : 1.0;
         if (tid == 0) s_fail = 0;
         __syncthreads();
 
-        for (int kb = 0; kb < Kp; kb += NB) {
-            // (i) factor the diagonal block with one wave (in-order LDS within a wave)
-            if (tid < 64) {
-                for (int f = tid; f < NB * NB; f += 64) {
-                    const int i = f / NB, j = f % NB;
-                    Ld[i][j] = W[(int64_t)(kb + j) * ld + kb + i];
-                }
-                __builtin_amdgcn_s_waitcnt(0);
-                __builtin_amdgcn_wave_barrier();
-                for (int j = 0; j < NB; ++j) {
-                    double dj = Ld[j][j];
-                    const bool bad = !(dj > PIV_TOL * diag0[kb + j]);
-                    dj = bad ? 1.0 : sqrt(dj);
-                    if (bad && tid == 0) s_fail = 1;
-                    __builtin_amdgcn_wave_barrier();
-                    if (tid == 0) Ld[j][j] = dj;
-                    if (tid > j && tid < NB) Ld[tid][j] /= dj;
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __builtin_amdgcn_wave_barrier();
-                    for (int f = tid; f < NB * NB; f += 64) {
-                        const int i = f / NB, c = f % NB;
-                        if (c > j && i >= c) Ld[i][c] -= Ld[i][j] * Ld[c][j];
+        for (int kb = 0; kb < Kp; kb += FB) {
+            // (i) diagonal block: lane i < FB holds row i in registers
+            if (wave == 0) {
+                double a[FB];
+#pragma unroll
+                for (int c = 0; c < FB; ++c)
+                    a[c] = (lane < FB && c <= lane) ? W[(int64_t)(kb + c) * ld + kb + lane] : 0.0;
+                bool bad = false;
+#pragma unroll
+                for (int j = 0; j < FB; ++j) {
+                    const double djj = readlane_f64(a[j], j);
+                    const bool b = !(djj > PIV_TOL * diag0[kb + j]);
+                    bad |= b;
+                    const double dj = b ? 1.0 : sqrt(djj);
+                    const double rd = 1.0 / dj;
+                    a[j] = (lane == j) ? dj : (lane > j ? a[j] * rd : a[j]);
+#pragma unroll
+                    for (int c = j + 1; c < FB; ++c) {
+                        const double lc = readlane_f64(a[j], c);   // L[c][j]
+                        if (lane >= c) a[c] = fma(-a[j], lc, a[c]);
                     }
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __builtin_amdgcn_wave_barrier();
                 }
-                for (int f = tid; f < NB * NB; f += 64) {
-                    const int i = f / NB, j = f % NB;
-                    if (i >= j) W[(int64_t)(kb + j) * ld + kb + i] = Ld[i][j];
+                if (lane == 0 && bad) s_fail = 1;
+                if (lane < FB) {
+#pragma unroll
+                    for (int c = 0; c < FB; ++c) {
+                        Ld[lane][c] = c <= lane ? a[c] : 0.0;
+                        if (c <= lane) W[(int64_t)(kb + c) * ld + kb + lane] = a[c];
+                    }
                 }
             }
             __syncthreads();
             if (s_fail) break;
-            // (ii) panel rows below the block (A rows and the B rows): x L^T = w
-            const int64_t r0 = kb + NB;
-            const int R = (int)(ld - r0);
-            const bool in_lds = R + 4 <= PANEL_LDS_ROWS;      // tiles read up to 3 rows past R
+            // (ii) panel rows below the block: x L_kk^T = w
+            const int r0 = kb + FB;
+            const int R = Kp - r0;
+            const bool in_lds = R <= PR;
             for (int rr = tid; rr < R; rr += CT) {
-                const int64_t i = r0 + rr;
-                double x[NB];
+                const int i = r0 + rr;
+                double x[FB];
 #pragma unroll
-                for (int c = 0; c < NB; ++c) x[c] = W[(int64_t)(kb + c) * ld + i];
+                for (int c = 0; c < FB; ++c) x[c] = W[(int64_t)(kb + c) * ld + i];
 #pragma unroll
-                for (int c = 0; c < NB; ++c) {
+                for (int c = 0; c < FB; ++c) {
                     double sacc = x[c];
 #pragma unroll
                     for (int cc = 0; cc < c; ++cc) sacc -= x[cc] * Ld[c][cc];
                     x[c] = sacc / Ld[c][c];
-                    __asm__ volatile("" ::: "memory");   // keep the LDS reads of row c here
+                    __asm__ volatile("" ::: "memory");     // keep the LDS reads of row c here
                 }
 #pragma unroll
-                for (int c = 0; c < NB; ++c) W[(int64_t)(kb + c) * ld + i] = x[c];
+                for (int c = 0; c < FB; ++c) W[(int64_t)(kb + c) * ld + i] = x[c];
                 if (in_lds) {
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) panel[c * PANEL_LDS_ROWS + rr] = x[c];
+                    for (int c = 0; c < FB; ++c) panel[c * PR + rr] = x[c];
                 }
             }
             __syncthreads();
-            // (iii) trailing update W[i][j] -= sum_c X[i][c] X[j][c] for j in [r0, Kp), i in [j, ld):
-            //       4x4 register tiles, row-block fastest across threads (a wave touches 2 KB of a
-            //       column at a time); X from the transposed LDS panel (4 rows of a lane = one
-            //       32-byte read, the j values broadcast) or from global memory
-            const int nj = Kp - (int)r0;
-            if (nj > 0) {
-                const int tj = (nj + 3) / 4, ti = (R + 3) / 4;
-                for (int t = tid; t < tj * ti; t += CT) {
-                    const int bi = t % ti, bj = t / ti;
-                    const int jl = 4 * bj, il = 4 * bi;       // local (panel) row indices
-                    if (il + 3 < jl) continue;                // tile entirely above the diagonal
-                    double acc[4][4];
+            // (iii) trailing update of the lower triangle: 16 x 16 tiles (ib >= jb) on MFMA
+            const int T16 = R / 16;                      // R is a multiple of 32
+            const int ntile = T16 * (T16 + 1) / 2;
+            for (int t = wave; t < ntile; t += CT / 64) {
+                // t -> (ib, jb), ib >= jb, enumerated row by row
+                int ib = (int)((sqrtf(8.f * t + 1.f) - 1.f) * 0.5f);
+                while ((ib + 1) * (ib + 2) / 2 <= t) ++ib;
+                while (ib * (ib + 1) / 2 > t) --ib;
+                const int jb = t - ib * (ib + 1) / 2;
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+                const int ri = 16 * ib + (lane & 15), rj = 16 * jb + (lane & 15), kq = lane >> 4;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 2
-                    for (int c = 0; c < NB; ++c) {
-                        double xi[4], xj[4];
-                        if (in_lds) {
-                            const double* pc = panel + c * PANEL_LDS_ROWS;
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                xi[u] = pc[il + u];     // rows >= R hold finite junk; never stored
-                                xj[u] = pc[jl + u];
-                            }
-                        } else {
-                            const double* colc = W + (int64_t)(kb + c) * ld + r0;
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                xi[u] = il + u < R ? colc[il + u] : 0.0;
-                                xj[u] = jl + u < nj ? colc[jl + u] : 0.0;
-                            }
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) acc[u][v] += xi[u] * xj[v];
+                for (int kc = 0; kc < FB; kc += 4) {
+                    double av, bv;
+                    if (in_lds) {
+                        av = panel[(kc + kq) * PR + ri];
+                        bv = panel[(kc + kq) * PR + rj];
+                    } else {
+                        av = W[(int64_t)(kb + kc + kq) * ld + r0 + ri];
+                        bv = W[(int64_t)(kb + kc + kq) * ld + r0 + rj];
                     }
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+                // FP64 16x16x4 output: D[i][j] sits in lane j + 16 (i % 4), register i / 4, so
+                // acc[q] = sum_k X[16 ib + kq + 4 q][k] X[16 jb + (lane & 15)][k]
+                const int col = r0 + 16 * jb + (lane & 15);
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int j = jl + v;
-                        if (j >= nj) continue;
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int i = il + u;
-                            if (i < j || i >= R) continue;
-                            W[(r0 + j) * ld + r0 + i] -= acc[u][v];
-                        }
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const int row = r0 + 16 * ib + kq + 4 * q;
+                    W[(int64_t)col * ld + row] -= acc[q];
                 }
             }
             __syncthreads();
         }
         if (!s_fail) break;
-        if (attempt == 0 && tid == 0) atomicOr(&status[4 * blockIdx.x + 1], 1);
+        if (attempt == 0 && tid == 0) atomicOr(&st[1], 1);
         if (attempt == 1 && tid == 0) {
-            atomicOr(&status[4 * blockIdx.x + 2], 1);
+            atomicOr(&st[2], 1);
+            st[4] = 1;
             s_failed_final = 1;
         }
         __syncthreads();
     }
     if (s_failed_final) return;
+    // mirror: W[i * ld + j] = L[i][j] for j < i (the upper triangle of the Kp x Kp block)
+    const int total = Kp * Kp;
+    for (int f = tid; f < total; f += CT) {
+        const int i = f / Kp, j = f - i * Kp;
+        if (j < i) W[(int64_t)i * ld + j] = W[(int64_t)j * ld + i];
+    }
+}
 
-    // D L = Z (Z = rows Kp .. Kp+m of W, D overwrites Z): blocks of NB columns from the right.
-    // Z[:, blk] -= D[:, right] L[right, blk] accumulated over 64-row chunks of D and L staged in
-    // LDS by all threads (every thread owns outputs (r, c); a wave shares c), then the small
-    // triangle D[:, blk] L[blk, blk] = Z[:, blk] row by row with L[blk, blk] in LDS.
-    {
-        // chunk rows so that D (CH x m) and L (CH x NB) fit in the panel buffer
-        const int CH = 64 * (m + NB) <= PANEL_LDS_ROWS * NB ? 64 : 32;
-        double* Dc = panel;                    // CH x m   (D[r][i0 + i] at Dc[i * m + r])
-        double* Lc = panel + CH * m;           // CH x NB
-        const int n_out = m * NB;
-        constexpr int OPT = (SMDL_MAX_M * NB + CT - 1) / CT;   // outputs per thread (max)
-        for (int jb = Kp - NB; jb >= 0; jb -= NB) {
-            const int je = jb + NB;
-            double acc[OPT];
-#pragma unroll
-            for (int q = 0; q < OPT; ++q) acc[q] = 0.0;
-            for (int i0 = je; i0 < Kp; i0 += CH) {
-                const int nr = Kp - i0 < CH ? Kp - i0 : CH;
-                for (int f = tid; f < nr * m; f += CT) {
-                    const int i = f / m, r = f - i * m;
-                    Dc[i * m + r] = W[(int64_t)(i0 + i) * ld + Kp + r];
-                }
-                for (int f = tid; f < nr * NB; f += CT) {
-                    const int c = f / nr, i = f - c * nr;
-                    Lc[i * NB + c] = W[(int64_t)(jb + c) * ld + i0 + i];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < OPT; ++q) {
-                    const int o = tid + q * CT;
-                    if (o < n_out) {
-                        const int r = o % m, c = o / m;
-                        double s0 = 0.0, s1 = 0.0;
-                        int i = 0;
-                        for (; i + 2 <= nr; i += 2) {
-                            s0 += Dc[i * m + r] * Lc[i * NB + c];
-                            s1 += Dc[(i + 1) * m + r] * Lc[(i + 1) * NB + c];
-                        }
-                        if (i < nr) s0 += Dc[i * m + r] * Lc[i * NB + c];
-                        acc[q] += s0 + s1;
-                    }
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int q = 0; q < OPT; ++q) {
-                const int o = tid + q * CT;
-                if (o < n_out) {
-                    const int r = o % m, c = o / m;
-                    W[(int64_t)(jb + c) * ld + Kp + r] -= acc[q];
-                }
-            }
-            for (int f = tid; f < NB * NB; f += CT) {
-                const int i = f / NB, j = f % NB;
-                Ld[i][j] = i >= j ? W[(int64_t)(jb + j) * ld + jb + i] : 0.0;
-            }
-            __syncthreads();
-            for (int r = tid; r < m; r += CT) {
-                const int64_t zr = Kp + r;
-                double x[NB];
-#pragma unroll
-                for (int c = 0; c < NB; ++c) x[c] = W[(int64_t)(jb + c) * ld + zr];
-#pragma unroll
-                for (int c = NB - 1; c >= 0; --c) {
-                    double sacc = x[c];
-#pragma unroll
-                    for (int i = c + 1; i < NB; ++i) sacc -= x[i] * Ld[i][c];
-                    x[c] = sacc / Ld[c][c];
-                    __asm__ volatile("" ::: "memory");
-                }
-#pragma unroll
-                for (int c = 0; c < NB; ++c) W[(int64_t)(jb + c) * ld + zr] = x[c];
-            }
-            __syncthreads();
+// ------------------------------------------------------------------------------------------
+// Solve D A = B row by row: z L^T = b, then d L = z (grid: (ceil(m / 4), dictionaries))
+// ------------------------------------------------------------------------------------------
+// One wave per row of D (4 rows per block share the LDS copies of L's diagonal chunks).  Chunks
+// of 64 columns: the contributions of the solved chunks are dot products over coalesced loads of
+// L (lower part for the forward pass, the mirrored upper part for the backward pass); inside the
+// chunk, 64 sequential steps with the chunk's diagonal block in LDS.  The solution overwrites the
+// B rows of W (W[j * ld + Kp + r] = D[r][j]).
+constexpr int SC = 64;
+
+__global__ __launch_bounds__(256) void tri_solve_kernel(const ModDesc* __restrict__ md, int m,
+                                                        const int32_t* __restrict__ status) {
+    const int t = blockIdx.y;
+    if (status[8 * t + 4]) return;
+    const ModDesc d = md[t];
+    const int Kp = d.Kpad;
+    const int ld = Kp + m;
+    const double* P = d.A;
+    double* W = d.W;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = blockIdx.x * 4 + wave;
+    const bool row_ok = r < m;
+    __shared__ double Lb[SC][SC + 1];
+    __shared__ double zs[4][SMDL_MAX_K];
+    // forward: z_j = (b_j - sum_{i<j} L[j][i] z_i) / L[j][j]
+    for (int J = 0; J < Kp; J += SC) {
+        for (int f = threadIdx.x; f < SC * SC; f += 256) {
+            const int c = f / SC, i = f % SC;                 // Lb[i][c] = L[J+i][J+c]
+            Lb[i][c] = i >= c ? W[(int64_t)(J + c) * ld + J + i] : 0.0;
         }
-    }
-    // normalise and store the active atoms (one wave per atom)
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int j = wv; j < d.K; j += CT / 64) {
-        if (!active[j]) continue;
-        double ss = 0.0;
-        for (int r = lane; r < m; r += 64) {
-            const double v = W[(int64_t)j * ld + Kp + r];
-            ss += v * v;
+        const int j = J + lane;
+        double tj = row_ok ? P[(int64_t)j * ld + Kp + r] : 0.0;
+        double s0 = 0.0, s1 = 0.0;
+        int i = 0;
+        for (; i + 2 <= J; i += 2) {
+            s0 += W[(int64_t)i * ld + j] * zs[wave][i];
+            s1 += W[(int64_t)(i + 1) * ld + j] * zs[wave][i + 1];
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
-        const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 1.0;
-        for (int r = lane; r < m; r += 64) d.D[(int64_t)j * m + r] = (float)(W[(int64_t)j * ld + Kp + r] * inv);
+        for (; i < J; ++i) s0 += W[(int64_t)i * ld + j] * zs[wave][i];
+        tj -= s0 + s1;
+        __syncthreads();
+        for (int jj = 0; jj < SC; ++jj) {
+            const double zj = readlane_f64(tj / Lb[lane][lane], jj);
+            if (lane > jj) tj = fma(-Lb[lane][jj], zj, tj);
+            if (lane == jj) tj = zj;
+        }
+        zs[wave][j] = tj;
+        __syncthreads();
     }
+    // backward: d_j = (z_j - sum_{i>j} L[i][j] d_i) / L[j][j], L[i][j] = W[i * ld + j] (mirror)
+    for (int J = Kp - SC; J >= 0; J -= SC) {
+        for (int f = threadIdx.x; f < SC * SC; f += 256) {
+            const int c = f / SC, i = f % SC;
+            Lb[i][c] = i >= c ? W[(int64_t)(J + c) * ld + J + i] : 0.0;
+        }
+        const int j = J + lane;
+        double tj = zs[wave][j];
+        double s0 = 0.0, s1 = 0.0;
+        int i = J + SC;
+        for (; i + 2 <= Kp; i += 2) {
+            s0 += W[(int64_t)i * ld + j] * zs[wave][i];
+            s1 += W[(int64_t)(i + 1) * ld + j] * zs[wave][i + 1];
+        }
+        for (; i < Kp; ++i) s0 += W[(int64_t)i * ld + j] * zs[wave][i];
+        tj -= s0 + s1;
+        __syncthreads();
+        for (int jj = SC - 1; jj >= 0; --jj) {
+            const double dj = readlane_f64(tj / Lb[lane][lane], jj);
+            if (lane < jj) tj = fma(-Lb[jj][lane], dj, tj);
+            if (lane == jj) tj = dj;
+        }
+        zs[wave][j] = tj;                                    // z of this chunk is now d
+        __syncthreads();
+    }
+    if (row_ok)
+        for (int j = lane; j < Kp; j += 64) W[(int64_t)j * ld + Kp + r] = zs[wave][j];
+}
+
+// Unit-normalise the solved atoms and store them (one wave per atom).
+__global__ __launch_bounds__(256) void mod_normalize_kernel(const ModDesc* __restrict__ md, int m,
+                                                            const int32_t* __restrict__ status) {
+    const int t = blockIdx.y;
+    if (status[8 * t + 4]) return;
+    const ModDesc d = md[t];
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= d.K) return;
+    const int ld = d.Kpad + m;
+    if (!(d.A[(int64_t)j * ld + j] > 0.0)) return;      // unused atom: keep its value
+    const double* col = d.W + (int64_t)j * ld + d.Kpad;
+    double ss = 0.0;
+    for (int r = lane; r < m; r += 64) ss += col[r] * col[r];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 1.0;
+    for (int r = lane; r < m; r += 64) d.D[(int64_t)j * m + r] = (float)(col[r] * inv);
 }
 
 inline int grid_sig(int64_t n) {
@@ -460,6 +475,10 @@ hipError_t launch_mod(const ModDesc* dev_desc, const ModDesc* host_desc, int n_d
     hipLaunchKernelGGL(mod_products_kernel, dim3(max_kpad, n_desc), dim3(256), 0, st, dev_desc, m, ptr,
                        list_sig, list_coef);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status);
+    hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(tri_solve_kernel, dim3((m + 3) / 4, n_desc), dim3(256), 0, st, dev_desc, m, status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(mod_normalize_kernel, dim3((max_kpad + 3) / 4, n_desc), dim3(256), 0, st, dev_desc, m, status);
     return hipGetLastError();
 }

@@ -11,7 +11,9 @@
 //     g_i   = G[j, sel_i] (i < k), G_jj     (broadcast loads), row G[j, :] (coalesced float4)
 //     w     = Linv g                        (Linv = inverse Cholesky factor of G_II)
 //     l^2   = G_jj - w.w                    (squared distance of d_j to span D_I)
-//     u     = (G[:, j] - U w) / l           (correlations of the new orthonormal direction)
+//     u     = (G[:, j] - U w) / l           (correlations of the new orthonormal direction;
+//                                            U holds the unscaled vectors, the 1/l factors are
+//                                            applied to the k coefficients instead)
 //     pi_k  = c_j / l ;  c -= pi_k u ;  ||r||^2 -= pi_k^2
 //     Linv row k = (-(w^T Linv)/l, 1/l)
 //   and finally x_I = Linv^T pi.  This is OMP (least squares on the support at every step)
@@ -42,7 +44,9 @@ __device__ __forceinline__ float f4get(const float4& v, int e) {
 // (value, index) combine of the argmax: larger |value| wins, the lower index on equal |value|.
 // The order is total, so any reduction tree gives the same winner.
 __device__ __forceinline__ void argmax_combine(float& bv, int& bi, float ov, int oi) {
-    const bool take = fabsf(ov) > fabsf(bv) || (fabsf(ov) == fabsf(bv) && oi < bi);
+    // bitwise (non short-circuit) so the compiler emits compares and selects, not branches
+    const float ao = fabsf(ov), ab = fabsf(bv);
+    const bool take = (ao > ab) | ((ao == ab) & (oi < bi));
     bv = take ? ov : bv;
     bi = take ? oi : bi;
 }
@@ -77,6 +81,7 @@ struct State {
     float U[SM][EM];
     float Linv[SM][SM];
     float pi[SM];
+    float rl[SM];        // 1 / l_k of every step
     int sel[SM];
     float rn2;
     int k;
@@ -98,14 +103,16 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
     if (!__any(st.live)) return false;
     const int g = x.g;
     // argmax |c| over the group, lowest atom index on equal magnitude
+    // entries t >= E hold exact zeros (their alpha0, G rows and U stay zero), so they never
+    // win against a real entry and need no guard here
     float bv = st.c[0];
     int bi = 4 * g;
 #pragma unroll
     for (int t = 1; t < EM; ++t) {
-        if (t < x.E) {
-            const int e = 4 * G * (t >> 2) + 4 * g + (t & 3);
-            if (fabsf(st.c[t]) > fabsf(bv)) { bv = st.c[t]; bi = e; }
-        }
+        const int e = 4 * G * (t >> 2) + 4 * g + (t & 3);
+        const bool take = fabsf(st.c[t]) > fabsf(bv);
+        bv = take ? st.c[t] : bv;
+        bi = take ? e : bi;
     }
     group_argmax<G>(bv, bi);
     const int j = bi;
@@ -140,8 +147,7 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
         if (!(l2 > x.dep_tol * gjj)) {
             st.live = false;
         } else {
-            const float ell = sqrtf(l2);
-            const float rl = 1.0f / ell;
+            const float rl = __builtin_amdgcn_rsqf(l2);      // 1 / l (v_rsq_f32, 1 ulp)
 #pragma unroll
             for (int l = 0; l < KK; ++l) {
                 float acc = 0.f;
@@ -151,17 +157,21 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
             }
             st.Linv[KK][KK] = rl;
             const float pk = cj * rl;
+            // U keeps the unscaled direction v_k = G[:, j] - sum_i u_i w_i, u_k = v_k / l_k: the
+            // scale moves onto the k coefficients (w_i / l_i) and onto pi_k / l_k
+            float wv[KK > 0 ? KK : 1];
+#pragma unroll
+            for (int i = 0; i < KK; ++i) wv[i] = w[i] * st.rl[i];
+            const float pkr = pk * rl;
 #pragma unroll
             for (int t = 0; t < EM; ++t) {
-                if (t < x.E) {
-                    float u = gr[t];
+                float v = gr[t];
 #pragma unroll
-                    for (int i = 0; i < KK; ++i) u = fmaf(-st.U[i][t], w[i], u);
-                    u *= rl;
-                    st.U[KK][t] = u;
-                    st.c[t] = fmaf(-pk, u, st.c[t]);
-                }
+                for (int i = 0; i < KK; ++i) v = fmaf(-st.U[i][t], wv[i], v);
+                st.U[KK][t] = v;
+                st.c[t] = fmaf(-pkr, v, st.c[t]);
             }
+            st.rl[KK] = rl;
             st.pi[KK] = pk;
             st.sel[KK] = j;
             st.rn2 = fmaf(-pk, pk, st.rn2);

@@ -23,7 +23,7 @@ constexpr int EC = MAXC / GR;   // candidate entries per lane
 // the 16 lanes (DPP butterfly inside the row: larger logit, lower atom on ties) and the owner
 // advances past it.  The chosen atoms are then written in increasing atom order.
 __device__ __forceinline__ void tk_combine(float& bv, int& bi, float ov, int oi) {
-    const bool take = ov > bv || (ov == bv && oi < bi);
+    const bool take = (ov > bv) | ((ov == bv) & (oi < bi));
     bv = take ? ov : bv;
     bi = take ? oi : bi;
 }
@@ -41,7 +41,8 @@ template <int CTRL>
 __device__ __forceinline__ void ro_dpp(float& bv, int& bp) {
     const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bv), CTRL, 0xf, 0xf, false));
     const int op = __builtin_amdgcn_mov_dpp(bp, CTRL, 0xf, 0xf, false);
-    const bool take = fabsf(ov) > fabsf(bv) || (fabsf(ov) == fabsf(bv) && op < bp);
+    const float ao = fabsf(ov), ab = fabsf(bv);
+    const bool take = (ao > ab) | ((ao == ab) & (op < bp));
     bv = take ? ov : bv;
     bp = take ? op : bp;
 }
@@ -164,7 +165,7 @@ __device__ __forceinline__ bool r_step(RState<SM>& st, const RCtx& x) {
         if (!(l2 > a.dep_tol * gjj)) {
             st.live = false;
         } else {
-            const float rl = 1.0f / sqrtf(l2);
+            const float rl = __builtin_amdgcn_rsqf(l2);
 #pragma unroll
             for (int l = 0; l < KK; ++l) {
                 float acc = 0.f;

@@ -425,7 +425,7 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
     plan.ptr = (int32_t*)h->ws((t + ".ptr").c_str(), (total_atoms + 1) * 4);
     plan.list_sig = (int32_t*)h->ws((t + ".ls").c_str(), std::max<int64_t>(1, entries) * 4);
     plan.list_coef = (float*)h->ws((t + ".lc").c_str(), std::max<int64_t>(1, entries) * 4);
-    plan.status = (int32_t*)h->ws((t + ".status").c_str(), 4 * specs.size() * 4);
+    plan.status = (int32_t*)h->ws((t + ".status").c_str(), 8 * specs.size() * 4);
     plan.desc = (ModDesc*)h->ws((t + ".md").c_str(), specs.size() * sizeof(ModDesc));
     if (!A || !W || !plan.cnt || !plan.fill || !plan.ptr || !plan.list_sig || !plan.list_coef ||
         !plan.status || !plan.desc)
@@ -444,7 +444,7 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
     smdl_status st = h->hip(hipMemcpyAsync(plan.desc, md.data(), md.size() * sizeof(ModDesc),
                                            hipMemcpyHostToDevice, h->stream), "upload");
     if (st != SMDL_OK) return st;
-    return h->hip(launch_zero_i32(plan.status, 4 * (int64_t)specs.size(), h->stream), "zero");
+    return h->hip(launch_zero_i32(plan.status, 8 * (int64_t)specs.size(), h->stream), "zero");
 }
 
 hipError_t enqueue_mod(smdl_t h, const ModPlan& plan) {
@@ -455,15 +455,15 @@ hipError_t enqueue_mod(smdl_t h, const ModPlan& plan) {
 
 // Read the MOD status array; returns SMDL_E_NUMERIC / SMDL_E_ARG on failures.
 smdl_status read_mod_status(smdl_t h, const ModPlan& plan, std::vector<int32_t>* st_out) {
-    std::vector<int32_t> st(4 * plan.n_desc);
+    std::vector<int32_t> st(8 * plan.n_desc);
     smdl_status s = h->hip(hipMemcpyAsync(st.data(), plan.status, st.size() * 4, hipMemcpyDeviceToHost,
                                           h->stream), "status");
     if (s != SMDL_OK) return s;
     if ((s = h->hip(hipStreamSynchronize(h->stream), "mod")) != SMDL_OK) return s;
     if (st_out) *st_out = st;
     for (int i = 0; i < plan.n_desc; ++i) {
-        if (st[4 * i + 3]) return h->fail(SMDL_E_ARG, "codes hold an atom index outside [0, K) or nnz outside [0, s_max]");
-        if (st[4 * i + 2]) return h->fail(SMDL_E_NUMERIC, "FP64 Cholesky of X X^T failed after the ridge retry");
+        if (st[8 * i + 3]) return h->fail(SMDL_E_ARG, "codes hold an atom index outside [0, K) or nnz outside [0, s_max]");
+        if (st[8 * i + 2]) return h->fail(SMDL_E_NUMERIC, "FP64 Cholesky of X X^T failed after the ridge retry");
     }
     return SMDL_OK;
 }
