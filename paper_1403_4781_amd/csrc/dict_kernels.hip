@@ -40,10 +40,16 @@ __global__ void pack_dict_kernel(const PackDesc* __restrict__ pd, int m, int mch
 __global__ __launch_bounds__(256) void gram_kernel(const GramDesc* __restrict__ gd, int mchunks) {
     const GramDesc p = gd[blockIdx.y];
     const int nt = p.Kpad >> 6;
+    const int ntl = p.ld >> 6;        // 64-column tiles of a padded row
     const int tile = blockIdx.x;
-    if (tile >= nt * nt) return;
-    const int tr = tile / nt, tc = tile % nt;
+    if (tile >= nt * ntl) return;
+    const int tr = tile / ntl, tc = tile % ntl;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (tc >= nt) {                   // padding columns of rows 64 tr .. 64 tr + 63
+        for (int i = threadIdx.x; i < 64 * 64; i += 256)
+            p.G[(size_t)(64 * tr + (i >> 6)) * p.ld + 64 * tc + (i & 63)] = 0.f;
+        return;
+    }
     const int NRB = p.Kpad >> 4;
     const int rb = 4 * tr + wave;
     f32x4 acc[4];
@@ -74,7 +80,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const GramDesc* __restrict__ 
         for (int q = 0; q < 4; ++q) {
             const int row = 16 * rb + 4 * kq + q;
             const int col = 16 * (4 * tc + cb) + i16;
-            p.G[(size_t)row * p.Kpad + col] = acc[cb][q];
+            p.G[(size_t)row * p.ld + col] = acc[cb][q];
         }
 }
 
@@ -193,7 +199,7 @@ hipError_t launch_pack_dict_m(const void* dev_pack_desc, int n_dict, int max_kpa
 hipError_t launch_gram_batched(const void* dev_gram_desc, int n_dict, int max_kpad, int mchunks,
                                hipStream_t st) {
     const int nt = max_kpad / 64;
-    dim3 grid(nt * nt, n_dict);
+    dim3 grid(nt * (gram_ld(max_kpad) / 64), n_dict);
     hipLaunchKernelGGL(gram_kernel, grid, dim3(256), 0, st,
                        static_cast<const GramDesc*>(dev_gram_desc), mchunks);
     return hipGetLastError();

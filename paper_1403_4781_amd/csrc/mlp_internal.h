@@ -35,7 +35,8 @@ hipError_t launch_to_bf16(const float* w, int64_t n, int cols, int rows, uint16_
 // Proposer-restricted OMP.
 struct RestrictedArgs {
     const float* D;          // m x K
-    const float* gram;       // Kpad x Kpad
+    const float* gram;       // Kpad rows of gld floats
+    int gld;
     int Kpad, m, K;
     const float* Y;
     int64_t N;

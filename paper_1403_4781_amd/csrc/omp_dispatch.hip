@@ -13,10 +13,12 @@ namespace {
 struct TileEntry {
     int EM, SM, G, TT;
     hipError_t (*fn)(const OmpArgs&, int, hipStream_t, int);
+    size_t (*lds)(int);
 };
 
 const TileEntry kTiles[] = {
-#define SMDL_OMP_TILE(EM, SM, G, TT) {EM, SM, G, TT, &smdl_omp::launch_one<EM, SM, G, TT>},
+#define SMDL_OMP_TILE(EM, SM, G, TT) \
+    {EM, SM, G, TT, &smdl_omp::launch_one<EM, SM, G, TT>, &smdl_omp::omp_lds_size<SM, G, TT>},
 #include "omp_table.inc"
 #undef SMDL_OMP_TILE
 };
@@ -36,19 +38,21 @@ const TileEntry* find_tile(OmpTile t, int Kpad, int s) {
 
 }  // namespace
 
-size_t omp_lds_bytes(OmpTile t, int maxKpad) {
-    const int T = 16 * t.tt;
-    return (size_t)T * (maxKpad + 4) * 4 + T * 4;
+// LDS of the instantiation that serves (t, maxKpad, s); 0 when there is none.
+size_t omp_lds_bytes(OmpTile t, int maxKpad, int s) {
+    const TileEntry* e = find_tile(t, maxKpad, s);
+    return e ? e->lds(maxKpad) : 0;
 }
 
-// A tile is usable when it is instantiated for (Kpad, s) and its alpha0 staging fits in the
-// 160 KB of LDS of a gfx950 workgroup.
+// A tile is usable when it is instantiated for (Kpad, s) and its LDS (alpha0 staging and the
+// greedy-loop slots) fits in the 160 KB of a gfx950 workgroup.
 bool omp_tile_supported(OmpTile t, int Kpad, int s) {
-    return find_tile(t, Kpad, s) != nullptr && omp_lds_bytes(t, Kpad) <= SMDL_LDS_BYTES;
+    const TileEntry* e = find_tile(t, Kpad, s);
+    return e != nullptr && e->lds(Kpad) <= SMDL_LDS_BYTES;
 }
 
 hipError_t launch_omp(OmpTile t, int maxKpad, int maxS, const OmpArgs& a, int grid, hipStream_t st) {
     const TileEntry* e = find_tile(t, maxKpad, maxS);
-    if (!e || omp_lds_bytes(t, maxKpad) > SMDL_LDS_BYTES) return hipErrorInvalidValue;
+    if (!e || e->lds(maxKpad) > SMDL_LDS_BYTES) return hipErrorInvalidValue;
     return e->fn(a, grid, st, maxKpad);
 }

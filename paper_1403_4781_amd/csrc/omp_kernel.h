@@ -41,58 +41,120 @@ __device__ __forceinline__ float f4get(const float4& v, int e) {
 }
 
 
-// (value, index) combine of the argmax: larger |value| wins, the lower index on equal |value|.
-// The order is total, so any reduction tree gives the same winner.
-__device__ __forceinline__ void argmax_combine(float& bv, int& bi, float ov, int oi) {
-    // bitwise (non short-circuit) so the compiler emits compares and selects, not branches
-    const float ao = fabsf(ov), ab = fabsf(bv);
-    const bool take = (ao > ab) | ((ao == ab) & (oi < bi));
-    bv = take ? ov : bv;
-    bi = take ? oi : bi;
-}
-
+// Group all-reduces over the G lanes of a signal (G = 16, 32 or 64; groups are aligned).
+// Within a row of 16 lanes: DPP quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror, each folded into the max / min instruction; across rows: lane shuffles.
+// DPP read of a neighbour lane; `ident` (the identity of the combining operation) stands for
+// lanes the pattern leaves out, which lets the compiler fold the read into the max / min.
 template <int CTRL>
-__device__ __forceinline__ void dpp_combine(float& bv, int& bi) {
-    const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bv), CTRL, 0xf, 0xf, false));
-    const int oi = __builtin_amdgcn_mov_dpp(bi, CTRL, 0xf, 0xf, false);
-    argmax_combine(bv, bi, ov, oi);
+__device__ __forceinline__ int dpp_i(int v, int ident) {
+    return __builtin_amdgcn_update_dpp(ident, v, CTRL, 0xf, 0xf, false);
 }
 
-// All-reduce of the argmax over the G lanes of a signal group (G = 16, 32 or 64; groups are
-// aligned).  Within a row of 16 lanes: DPP quad_perm [1,0,3,2], quad_perm [2,3,0,1],
-// row_half_mirror and row_mirror (VALU latency); across rows: lane shuffles.
+// Combine of a per-row (16-lane) result across the rows of a group of G = 32 or 64 lanes:
+// v_permlane16_swap exchanges rows 0 <-> 1 and 2 <-> 3 between its two operands,
+// v_permlane32_swap the halves; the max / min of the two outputs is the combined value.
 template <int G>
-__device__ __forceinline__ void group_argmax(float& bv, int& bi) {
-    dpp_combine<0xB1>(bv, bi);    // quad_perm [1,0,3,2]
-    dpp_combine<0x4E>(bv, bi);    // quad_perm [2,3,0,1]
-    dpp_combine<0x141>(bv, bi);   // row_half_mirror: quad q <-> quad 1-q within 8 lanes
-    dpp_combine<0x140>(bv, bi);   // row_mirror: half h <-> half 1-h within 16 lanes
-#pragma unroll
-    for (int off = 16; off < G; off <<= 1) {
-        const float ov = __shfl_xor(bv, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        argmax_combine(bv, bi, ov, oi);
+__device__ __forceinline__ int cross_rows(int v, bool take_max) {
+    if (G >= 32) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = take_max ? max((int)r[0], (int)r[1]) : min((int)r[0], (int)r[1]);
     }
+    if (G >= 64) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        v = take_max ? max((int)r[0], (int)r[1]) : min((int)r[0], (int)r[1]);
+    }
+    return v;
 }
 
+// Maximum of non-negative floats by their bit patterns (which order like the values).
+template <int G>
+__device__ __forceinline__ float group_max_nonneg(float f) {
+    int v = __float_as_int(f);
+    v = max(v, dpp_i<0xB1>(v, 0));
+    v = max(v, dpp_i<0x4E>(v, 0));
+    v = max(v, dpp_i<0x141>(v, 0));
+    v = max(v, dpp_i<0x140>(v, 0));
+    v = cross_rows<G>(v, true);
+    return __int_as_float(v);
+}
+
+template <int G>
+__device__ __forceinline__ int group_min(int v) {
+    v = min(v, dpp_i<0xB1>(v, 0x7fffffff));
+    v = min(v, dpp_i<0x4E>(v, 0x7fffffff));
+    v = min(v, dpp_i<0x141>(v, 0x7fffffff));
+    v = min(v, dpp_i<0x140>(v, 0x7fffffff));
+    return cross_rows<G>(v, false);
+}
+
+// Largest |c_t| of the lane (v_max3_f32 with |.| operand modifiers; exact).
+template <int EM>
+__device__ __forceinline__ float lane_max_abs(const float (&c)[EM]) {
+    float m[EM];
+#pragma unroll
+    for (int t = 0; t < EM; ++t) m[t] = fabsf(c[t]);
+#pragma unroll
+    for (int w = 1; w < EM; w *= 3)
+#pragma unroll
+        for (int t = 0; t < EM; t += 3 * w) {
+            if (t + w < EM) m[t] = fmaxf(m[t], m[t + w]);
+            if (t + 2 * w < EM) m[t] = fmaxf(m[t], m[t + 2 * w]);
+        }
+    return m[0];
+}
+
+// Sum over the G lanes of a group; every lane gets the same bits (each combine is a commutative
+// add of the same two values).
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+    v += __int_as_float(dpp_i<0xB1>(__float_as_int(v), 0));
+    v += __int_as_float(dpp_i<0x4E>(__float_as_int(v), 0));
+    v += __int_as_float(dpp_i<0x141>(__float_as_int(v), 0));
+    v += __int_as_float(dpp_i<0x140>(__float_as_int(v), 0));
+    if (G >= 32) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+        v = __int_as_float((int)r[0]) + __int_as_float((int)r[1]);
+    }
+    if (G >= 64) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+        v = __int_as_float((int)r[0]) + __int_as_float((int)r[1]);
+    }
+    return v;
+}
+
+// Per-signal state of the greedy loop, in registers.  The inverse Cholesky factor Linv of G_II
+// is held by columns: lane g of the group keeps column g (Linv[i][g], zero for i < g), and the
+// lane g < k keeps the atom chosen at step g.  Entries of step i are written only when the
+// signal is still live at step i and read only for i < k, so none needs initialising.
 template <int EM, int SM>
 struct State {
-    float c[EM];
-    float U[SM][EM];
-    float Linv[SM][SM];
-    float pi[SM];
-    float rl[SM];        // 1 / l_k of every step
-    int sel[SM];
-    float rn2;
-    int k;
+    float c[EM];         // correlations of the residual with this lane's atoms
+    float U[SM][EM];     // unscaled directions v_i = l_i u_i at this lane's atoms
+    float Lc[SM];        // Linv[i][g]
+    float pi[SM];        // pi_i = c_j / l_i of step i
+    float rl[SM];        // 1 / l_i
+    int sel;             // atom chosen at step g
+    float rn2;           // ||r||^2
+    int k;               // atoms chosen
     bool live;
 };
 
 struct StepCtx {
     const float* __restrict__ gram;
-    int E, s, g, Kpad;
+    const float* arow;   // alpha0 of the signal (LDS), atom 0
+    int g, s, gld, kpad;
     float eps2, tau, dep_tol, ynrm;
 };
+
+// Global loads at a 32-bit byte offset from a wave-uniform base (global_load with a scalar
+// base address and a 32-bit vector offset).
+__device__ __forceinline__ f32x4 gload4(const float* base, uint32_t byte_off) {
+    return *(const __attribute__((address_space(1))) f32x4*)(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ float gload(const float* base, uint32_t byte_off) {
+    return *(const __attribute__((address_space(1))) float*)(reinterpret_cast<const char*>(base) + byte_off);
+}
 
 // One greedy step (step index KK is a compile-time constant so that every register array
 // index below is static).  Returns false when the whole wave is done.
@@ -102,67 +164,64 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
     if (x.eps2 > 0.f && !(st.rn2 > x.eps2)) st.live = false;
     if (!__any(st.live)) return false;
     const int g = x.g;
-    // argmax |c| over the group, lowest atom index on equal magnitude
-    // entries t >= E hold exact zeros (their alpha0, G rows and U stay zero), so they never
-    // win against a real entry and need no guard here
-    float bv = st.c[0];
-    int bi = 4 * g;
+    // argmax |c| over the group: the exact maximum M, then the lowest atom index holding it.
+    // Entries t >= E hold exact zeros (their alpha0 and G rows are zero), so they never win.
+    const float M = group_max_nonneg<G>(lane_max_abs<EM>(st.c));
+    // lowest entry t of the lane with |c_t| == M: four independent chains (t % 4), then a min
+    int tq[4] = {EM, EM, EM, EM};
 #pragma unroll
-    for (int t = 1; t < EM; ++t) {
-        const int e = 4 * G * (t >> 2) + 4 * g + (t & 3);
-        const bool take = fabsf(st.c[t]) > fabsf(bv);
-        bv = take ? st.c[t] : bv;
-        bi = take ? e : bi;
-    }
-    group_argmax<G>(bv, bi);
-    const int j = bi;
-    const float cj = bv;
-    if (!(fabsf(cj) > x.tau * x.ynrm)) st.live = false;
+    for (int t = EM - 1; t >= 0; --t) tq[t & 3] = (fabsf(st.c[t]) == M) ? t : tq[t & 3];
+    const int tl = min(min(tq[0], tq[1]), min(tq[2], tq[3]));
+    const int el = tl < EM ? 4 * G * (tl >> 2) + 4 * g + (tl & 3) : 0x7fffffff;
+    const int j = group_min<G>(el);
+    // (j is a valid atom whenever M is a finite maximum; the test keeps any other case away
+    // from the loads below)
+    if (!(M > x.tau * x.ynrm) || (uint32_t)j >= (uint32_t)x.kpad) st.live = false;
     if (st.live) {
-        const float* grow = x.gram + (size_t)j * x.Kpad;
+        // 32-bit offsets from the (uniform) Gram base: global loads with a scalar base
+        const uint32_t row = (uint32_t)j * (uint32_t)x.gld * 4u;   // bytes
+        // row j of G at this lane's atoms (columns < EM * G <= gld: no guard needed)
         float gr[EM];
 #pragma unroll
         for (int q = 0; q < EM / 4; ++q) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (4 * q < x.E) v = *reinterpret_cast<const float4*>(grow + 4 * G * q + 4 * g);
-            gr[4 * q + 0] = v.x;
-            gr[4 * q + 1] = v.y;
-            gr[4 * q + 2] = v.z;
-            gr[4 * q + 3] = v.w;
+            const f32x4 v = gload4(x.gram, row + (uint32_t)(16 * G * q + 16 * g));
+            gr[4 * q + 0] = v[0];
+            gr[4 * q + 1] = v[1];
+            gr[4 * q + 2] = v[2];
+            gr[4 * q + 3] = v[3];
         }
-        float gs[KK > 0 ? KK : 1];
-#pragma unroll
-        for (int i = 0; i < KK; ++i) gs[i] = grow[st.sel[i]];
-        const float gjj = grow[j];
+        // lane g < k: G[j, sel_g]
+        const bool mine = g < KK;
+        float gsg = gload(x.gram, row + 4u * (uint32_t)(mine ? st.sel : j));
+        gsg = mine ? gsg : 0.f;
+        const float gjj = gload(x.gram, row + 4u * (uint32_t)j);
+        const float a0j = x.arow[j];
+        // w = Linv g (= u_i(j), the earlier directions at atom j): w_i = sum_g Linv[i][g] G[j, sel_g]
         float w[KK > 0 ? KK : 1];
         float l2 = gjj;
 #pragma unroll
         for (int i = 0; i < KK; ++i) {
-            float acc = 0.f;
-#pragma unroll
-            for (int l = 0; l <= i; ++l) acc = fmaf(st.Linv[i][l], gs[l], acc);
-            w[i] = acc;
-            l2 = fmaf(-acc, acc, l2);
+            w[i] = group_sum<G>(st.Lc[i] * gsg);
+            l2 = fmaf(-w[i], w[i], l2);
         }
-        if (!(l2 > x.dep_tol * gjj)) {
-            st.live = false;
-        } else {
+        // d_j (numerically) in the span of the chosen atoms: the signal stops here.  The update
+        // below runs regardless with a zero step, which leaves c unchanged, so that the G-row
+        // loads above are not held back behind this test.
+        const bool ok = l2 > x.dep_tol * gjj;
+        {
             const float rl = __builtin_amdgcn_rsqf(l2);      // 1 / l (v_rsq_f32, 1 ulp)
+            // c_j: magnitude M (the maintained value), sign of alpha0_j - sum_i pi_i u_i(j)
+            float cr = a0j;
 #pragma unroll
-            for (int l = 0; l < KK; ++l) {
-                float acc = 0.f;
-#pragma unroll
-                for (int i = l; i < KK; ++i) acc = fmaf(w[i], st.Linv[i][l], acc);
-                st.Linv[KK][l] = -acc * rl;
-            }
-            st.Linv[KK][KK] = rl;
+            for (int i = 0; i < KK; ++i) cr = fmaf(-st.pi[i], w[i], cr);
+            const float cj = copysignf(M, cr);
             const float pk = cj * rl;
             // U keeps the unscaled direction v_k = G[:, j] - sum_i u_i w_i, u_k = v_k / l_k: the
             // scale moves onto the k coefficients (w_i / l_i) and onto pi_k / l_k
             float wv[KK > 0 ? KK : 1];
 #pragma unroll
             for (int i = 0; i < KK; ++i) wv[i] = w[i] * st.rl[i];
-            const float pkr = pk * rl;
+            const float pkr = ok ? pk * rl : 0.f;
 #pragma unroll
             for (int t = 0; t < EM; ++t) {
                 float v = gr[t];
@@ -171,11 +230,17 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
                 st.U[KK][t] = v;
                 st.c[t] = fmaf(-pkr, v, st.c[t]);
             }
-            st.rl[KK] = rl;
+            // Linv row k = (-(w^T Linv) / l, 1 / l): lane g forms entry g
+            float hg = 0.f;
+#pragma unroll
+            for (int i = 0; i < KK; ++i) hg = fmaf(w[i], st.Lc[i], hg);
+            st.Lc[KK] = mine ? -hg * rl : (g == KK ? rl : 0.f);
             st.pi[KK] = pk;
-            st.sel[KK] = j;
-            st.rn2 = fmaf(-pk, pk, st.rn2);
-            st.k = KK + 1;
+            st.rl[KK] = rl;
+            st.sel = (g == KK) ? j : st.sel;
+            st.rn2 = ok ? fmaf(-pk, pk, st.rn2) : st.rn2;
+            st.k = ok ? KK + 1 : st.k;
+            st.live = ok;
         }
     }
     return true;
@@ -200,8 +265,6 @@ __global__ __launch_bounds__(256, 2) void omp_fused(OmpArgs a) {
     __shared__ OmpItem s_it;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
 
     int n_items = a.n_items;
     if (a.list_count) n_items = (*a.list_count + T - 1) / T;
@@ -230,8 +293,19 @@ __global__ __launch_bounds__(256, 2) void omp_fused(OmpArgs a) {
             }
         }
         __syncthreads();
-        const OmpItem it = s_it;
+        // the item is the same for the whole group: keep it (and so the descriptor) in SGPRs
+        OmpItem it;
+        it.desc = __builtin_amdgcn_readfirstlane(s_it.desc);
+        it.count = __builtin_amdgcn_readfirstlane(s_it.count);
+        it.first = ((int64_t)__builtin_amdgcn_readfirstlane((int)(s_it.first >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)s_it.first);
         const OmpDesc d = a.desc[it.desc];
+        // lane ids made opaque per item: otherwise the compiler hoists every lane-dependent
+        // address of both phases out of the item loop and keeps them all live in registers
+        int lid = tid & 63;
+        asm volatile("" : "+v"(lid));
+        const int lane = lid;
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
         const int Kpad = d.Kpad;
         const int stride = Kpad + 4;           // LDS row stride (floats) of alpha0
         float* alpha = lds;                    // T x stride
@@ -319,12 +393,18 @@ __global__ __launch_bounds__(256, 2) void omp_fused(OmpArgs a) {
         {
             const int g = lane % G;
             const int grp = lane / G;
+            const int E = Kpad / G;
             StepCtx ctx;
-            ctx.E = Kpad / G;
             ctx.s = d.s;
             ctx.g = g;
-            ctx.gram = d.gram;
-            ctx.Kpad = Kpad;
+            {
+                const uint64_t gp = reinterpret_cast<uint64_t>(d.gram);
+                ctx.gram = reinterpret_cast<const float*>(
+                    ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gp >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gp));
+            }
+            ctx.gld = d.gld;
+            ctx.kpad = Kpad;
             ctx.eps2 = a.eps2;
             ctx.tau = a.tau;
             ctx.dep_tol = a.dep_tol;
@@ -333,18 +413,12 @@ __global__ __launch_bounds__(256, 2) void omp_fused(OmpArgs a) {
                 const int sl = p * SPP + wave * GPW + grp;
                 const bool valid = sl < it.count;
                 State<EM, SM> st;
-#pragma unroll
-                for (int i = 0; i < SM; ++i) {
-                    st.pi[i] = 0.f;
-                    st.sel[i] = 0;
-#pragma unroll
-                    for (int l = 0; l <= i; ++l) st.Linv[i][l] = 0.f;
-                }
-                const float* arow = alpha + (valid ? sl : 0) * stride + 4 * g;
+                ctx.arow = alpha + (valid ? sl : 0) * stride;
+                const float* arow = ctx.arow + 4 * g;
 #pragma unroll
                 for (int q = 0; q < EM / 4; ++q) {
                     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (4 * q < ctx.E) v = *reinterpret_cast<const float4*>(arow + 4 * G * q);
+                    if (4 * q < E) v = *reinterpret_cast<const float4*>(arow + 4 * G * q);
                     st.c[4 * q + 0] = v.x;
                     st.c[4 * q + 1] = v.y;
                     st.c[4 * q + 2] = v.z;
@@ -357,24 +431,21 @@ __global__ __launch_bounds__(256, 2) void omp_fused(OmpArgs a) {
                 st.k = 0;
                 run_steps<EM, SM, G>(st, ctx, std::make_integer_sequence<int, SM>{});
                 if (valid) {
-                    // x_I = Linv^T pi
-                    float gam[SM];
-#pragma unroll
-                    for (int l = 0; l < SM; ++l) {
-                        float acc = 0.f;
-#pragma unroll
-                        for (int i = l; i < SM; ++i) acc = fmaf(st.Linv[i][l], (i < st.k) ? st.pi[i] : 0.f, acc);
-                        gam[l] = acc;
-                    }
                     int64_t sig = it.first + sl;
                     if (a.sig_list) sig = a.sig_list[sig];
                     else sig += d.out0;
                     if (g < a.s_out) {
+                        // x_I = Linv^T pi; lane g forms and writes entry g
                         int oi = -1;
                         float oc = 0.f;
+                        if (g < st.k) {
 #pragma unroll
-                        for (int i = 0; i < SM; ++i)
-                            if (i == g && i < st.k) { oi = st.sel[i]; oc = gam[i]; }
+                            for (int i = 0; i < SM; ++i) {
+                                const float t = fmaf(st.Lc[i], st.pi[i], oc);
+                                oc = (i < st.k) ? t : oc;
+                            }
+                            oi = st.sel;
+                        }
                         a.idx[sig * a.s_out + g] = oi;
                         a.coef[sig * a.s_out + g] = oc;
                     }
@@ -383,16 +454,22 @@ __global__ __launch_bounds__(256, 2) void omp_fused(OmpArgs a) {
                         if (a.res) a.res[sig] = sqrtf(fmaxf(st.rn2, 0.f));
                     }
                 }
+                __builtin_amdgcn_wave_barrier();
             }
         }
         __syncthreads();
     }
 }
 
+// Dynamic LDS of one work group: alpha0 (T rows of maxKpad + 4 floats) and ||y||^2 (T floats).
+template <int SM, int G, int TT>
+constexpr size_t omp_lds_size(int maxKpad) {
+    return ((size_t)16 * TT * (maxKpad + 4) + 16 * TT) * 4;
+}
+
 template <int EM, int SM, int G, int TT>
 hipError_t launch_one(const OmpArgs& a, int grid, hipStream_t st, int maxKpad) {
-    constexpr int T = 16 * TT;
-    const size_t lds = (size_t)T * (maxKpad + 4) * 4 + T * 4;
+    const size_t lds = omp_lds_size<SM, G, TT>(maxKpad);
     static size_t lds_enabled = 64 * 1024;   // dynamic LDS this instantiation may request
     if (lds > lds_enabled) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&omp_fused<EM, SM, G, TT>),

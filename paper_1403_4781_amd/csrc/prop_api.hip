@@ -416,6 +416,7 @@ extern "C" smdl_status smdl_omp_code_proposed(smdl_t h, smdl_prop_t p, const flo
     RestrictedArgs r{};
     r.D = D;
     r.gram = sets[0].gram;
+    r.gld = sets[0].gld;
     r.Kpad = sets[0].Kpad;
     r.m = m;
     r.K = K;

@@ -147,7 +147,7 @@ __device__ __forceinline__ bool r_step(RState<SM>& st, const RCtx& x) {
     if (!(fabsf(bv) > a.tau * x.ynrm) || bp >= a.n_cand) st.live = false;
     if (st.live) {
         const int j = a.cand[x.n * a.n_cand + bp];
-        const float* grow = a.gram + (int64_t)j * a.Kpad;
+        const float* grow = a.gram + (int64_t)j * a.gld;
         float gs[KK > 0 ? KK : 1];
 #pragma unroll
         for (int i = 0; i < KK; ++i) gs[i] = grow[st.sel[i]];

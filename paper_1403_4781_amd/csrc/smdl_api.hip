@@ -158,7 +158,7 @@ std::vector<OmpTile> candidate_tiles(int Kpad, int s, int lanes_ok) {
         for (int tt : {1, 2, 4}) {
             OmpTile t{lanes, tt};
             if (!(lanes & lanes_ok) || !omp_tile_supported(t, Kpad, s)) continue;
-            if (omp_lds_bytes(t, Kpad) > 96 * 1024) continue;
+            if (omp_lds_bytes(t, Kpad, s) > 96 * 1024) continue;
             out.push_back(t);
         }
     return out;
@@ -188,7 +188,11 @@ smdl_status prepare_sets(smdl_t h, int m, std::vector<SetSpec>& sets, const char
         for (int lanes : {16, 32, 64})
             if (s.Kpad % (4 * lanes)) plan.lanes_ok &= ~lanes;
         frag_total += (size_t)mpad * s.Kpad;
-        gram_total += (size_t)s.Kpad * s.Kpad;
+    }
+    const int gld = gram_ld(plan.maxKpad);
+    for (auto& s : sets) {
+        s.gld = gld;
+        gram_total += (size_t)s.Kpad * gld;
     }
     std::string t(tag);
     float* frag = (float*)h->ws((t + ".frag").c_str(), frag_total * 4);
@@ -203,10 +207,10 @@ smdl_status prepare_sets(smdl_t h, int m, std::vector<SetSpec>& sets, const char
         s.frag = reinterpret_cast<float4*>(frag + fo);
         s.gram = gram + go;
         fo += (size_t)mpad * s.Kpad;
-        go += (size_t)s.Kpad * s.Kpad;
+        go += (size_t)s.Kpad * s.gld;
         pd[i] = PackDesc{s.D, s.frag, s.K, s.Kpad};
-        gd[i] = GramDesc{s.frag, s.gram, s.Kpad, 0};
-        od[i] = OmpDesc{s.frag, s.gram, s.Y, s.n, s.out0, s.K, s.Kpad, s.s, 0};
+        gd[i] = GramDesc{s.frag, s.gram, s.Kpad, s.gld};
+        od[i] = OmpDesc{s.frag, s.gram, s.Y, s.n, s.out0, s.K, s.Kpad, s.s, s.gld};
     }
     plan.pack_desc = h->ws((t + ".pd").c_str(), pd.size() * sizeof(PackDesc));
     plan.gram_desc = h->ws((t + ".gd").c_str(), gd.size() * sizeof(GramDesc));
@@ -309,8 +313,8 @@ extern "C" smdl_status smdl_gram(smdl_t h, const float* D, int m, int K, float* 
                      "pack")) != SMDL_OK) return st;
     if ((st = h->hip(launch_gram_batched(plan.gram_desc, 1, plan.maxKpad, plan.mchunks, h->stream),
                      "gram")) != SMDL_OK) return st;
-    const int Kp = sets[0].Kpad;
-    if ((st = h->hip(hipMemcpy2DAsync(G, (size_t)K * 4, sets[0].gram, (size_t)Kp * 4, (size_t)K * 4, K,
+    const int ld = sets[0].gld;
+    if ((st = h->hip(hipMemcpy2DAsync(G, (size_t)K * 4, sets[0].gram, (size_t)ld * 4, (size_t)K * 4, K,
                                       hipMemcpyDeviceToDevice, h->stream), "copy")) != SMDL_OK) return st;
     return h->hip(hipStreamSynchronize(h->stream), "gram");
 }

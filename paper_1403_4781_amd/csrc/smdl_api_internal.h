@@ -48,6 +48,7 @@ struct SetSpec {
     int64_t out0 = 0;           // first output row of the set
     // filled by prepare_sets
     int Kpad = 0;
+    int gld = 0;                // Gram row stride (floats)
     float4* frag = nullptr;
     float* gram = nullptr;
 };

@@ -26,14 +26,23 @@ constexpr size_t SMDL_LDS_BYTES = 160 * 1024 - 256;
 // ((c * Kpad/16 + b) * 4 + q) * 64 + l holds D[atom 16b + l%16][row 64c + 16(l/16) + 4q .. +3].
 inline int pad64(int x) { return (x + 63) / 64 * 64; }
 
+// Row stride (floats) of the Gram matrices of one launch whose largest padded width is maxKpad:
+// the next power of two, at least 256.  Every instantiated OMP tile reads G-row spans of
+// EM * G <= this many floats, so the row loads need no bounds guard; columns past Kpad are zero.
+inline int gram_ld(int maxKpad) {
+    int ld = 256;
+    while (ld < maxKpad) ld *= 2;
+    return ld;
+}
+
 // One dictionary and the signals coded against it.
 struct OmpDesc {
     const float4* dfrag;  // packed fragments (mpad x Kpad floats)
-    const float* gram;    // Kpad x Kpad row-major Gram matrix (zero outside K x K)
+    const float* gram;    // Kpad rows of gld floats, row-major Gram matrix (zero outside K x K)
     const float* Y;       // signals (m floats each)
     int64_t n;            // number of signals in this set
     int64_t out0;         // output row of signal 0 of this set
-    int K, Kpad, s, pad_;
+    int K, Kpad, s, gld;
 };
 
 // A tile of up to T signals of one descriptor.
@@ -73,7 +82,7 @@ hipError_t launch_gram_batched(const void* dev_gram_desc, int n_dict, int max_kp
 bool omp_tile_supported(OmpTile t, int Kpad, int s);
 hipError_t launch_omp(OmpTile t, int maxKpad, int maxS, const OmpArgs& a, int grid,
                       hipStream_t st);
-size_t omp_lds_bytes(OmpTile t, int maxKpad);
+size_t omp_lds_bytes(OmpTile t, int maxKpad, int s);
 
 // Batched dictionary helpers (descriptor arrays live in device memory).
 struct PackDesc {
@@ -83,8 +92,8 @@ struct PackDesc {
 };
 struct GramDesc {
     const float4* dfrag;
-    float* G;
-    int Kpad, pad_;
+    float* G;             // Kpad rows of ld floats; columns Kpad .. ld-1 are written as zeros
+    int Kpad, ld;
 };
 
 // MOD descriptors.
