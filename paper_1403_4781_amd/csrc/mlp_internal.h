@@ -3,32 +3,68 @@
 
 #include "smdl_internal.h"
 
-struct GemmArgs {
-    const uint16_t* A;   // bf16
-    const uint16_t* B;   // bf16
+// C[M x N] = A[M x K] B[N x K]^T (BF16, FP32 accumulation) with a fused epilogue, applied in
+// this order: + bias[col]; BCE (when tmask is set: the value is the logit z of batch row `row`,
+// target bit col of tmask[rows[row]], replaced by (sigmoid(z) - t) * scale, loss terms added to
+// *loss); ReLU; ReLU-backward mask (zero where mask <= 0); zero for rows >= Mvalid.  Then the
+// value is stored as FP32 (rows < Mvalid only) and/or BF16 [M x N] (ld = ldo), BF16 transposed [N x M] (ld = ldt),
+// and summed per column over each 32-row block into colpart[M / 32][N].
+// M % 32 == 0, K % 32 == 0, N % 4 == 0, lda / ldb multiples of 8.
+struct NtArgs {
+    const uint16_t* A;
+    const uint16_t* B;
+    int lda, ldb;
     int M, N, K;
-    int lda, ldb, ldc;
-    const float* bias;          // optional, per output column
-    const uint16_t* mask_bf16;  // optional: zero the output where mask <= 0 (ReLU backward)
-    int ldmask;
+    int Mvalid;
+    const float* bias;
     int relu;
-    float* out_f32;             // optional
-    uint16_t* out_bf16;         // optional
-    int ksplit;                 // > 1: blockIdx.z takes K/ksplit of the reduction and adds its
-                                // partial into out_f32 with atomics (out_f32 zeroed beforehand)
+    const uint16_t* mask;
+    int ldmask;
+    const uint32_t* tmask;      // label bitmask rows of (K + 31) / 32 words
+    int tstride;
+    const int32_t* rows;        // sample of each batch row (NULL: row itself)
+    float scale;
+    double* loss;
+    float* out_f32;
+    uint16_t* out_bf16;
+    int ldo;
+    uint16_t* outT;
+    int ldt;
+    float* colpart;
 };
 
-hipError_t launch_gemm(const GemmArgs& g, bool AT, bool BT, bool big, hipStream_t st);
-hipError_t launch_transpose_bf16(const uint16_t* in, int rows, int cols, uint16_t* out, hipStream_t st);
-hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
-hipError_t launch_prep_input(const float* Y, int64_t B, int m, int mpad, int64_t Bpad, const int32_t* rows,
-                             uint16_t* h0, hipStream_t st);
-hipError_t launch_bce(const float* z, int64_t B, int64_t Bpad, int K, const int32_t* lidx, const int32_t* lnnz,
-                      int ls, const int32_t* rows, float scale, float* delta, uint16_t* delta_bf,
-                      double* loss_part, double* loss, hipStream_t st);
-hipError_t launch_colsum(const float* x, int64_t B, int N, float* out, hipStream_t st);
-hipError_t launch_adam(float* w, const float* g, float* m1, float* m2, int64_t n, int cols, int rows, float lr,
-                       float b1, float b2, float eps, int t, uint16_t* wbf, uint16_t* wbfT, hipStream_t st);
+// One layer of the grouped weight-gradient launch.
+struct WgLayer {
+    const uint16_t* dT;       // [wo x Bpad] BF16 deltas of the layer output, transposed
+    const uint16_t* hT;       // [wi x Bpad] BF16 layer input, transposed
+    const float* colpart;     // [nparts x wo] column sums of the FP32 deltas
+    int nparts;
+    int wo, wi;
+    float *W, *b, *mW, *vW, *mb, *vb;   // Adam: FP32 masters and moments
+    uint16_t *Wbf, *WbfT;               // Adam: BF16 copies (wo x wi) and (wi x wo)
+    float *dW_out, *db_out;             // gradient-only mode
+    int tile0, ntn;                     // set by the launcher
+};
+
+struct WgArgs {
+    WgLayer L[4];
+    int n_layers;
+    int Bpad;
+    int bias_block0;          // set by the launcher
+    int adam;
+    float lr, b1, b2, eps;
+    const int32_t* t_dev;     // Adam: steps taken before this launch's epoch (device) ...
+    int t_off;                // ... plus this: the step number t of the bias corrections
+};
+
+hipError_t launch_gemm_nt(const NtArgs& g, hipStream_t st);
+hipError_t launch_wgrad(WgArgs& g, hipStream_t st);
+hipError_t launch_prep(const float* Y, int64_t B, int m, int64_t Bpad, const int32_t* rows, uint16_t* h0,
+                       uint16_t* h0T, hipStream_t st);
+hipError_t launch_label_mask(const int32_t* idx, const int32_t* nnz, int ls, int64_t N, int K, uint32_t* mask,
+                             hipStream_t st);
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
+hipError_t launch_add_i32(int32_t* p, int32_t v, hipStream_t st);
 hipError_t launch_to_bf16(const float* w, int64_t n, int cols, int rows, uint16_t* wbf, uint16_t* wbfT,
                           hipStream_t st);
 

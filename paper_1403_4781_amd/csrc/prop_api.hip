@@ -16,7 +16,8 @@ struct smdl_prop {
     std::vector<int> widths;
     std::vector<float*> W, b, mW, vW, mb, vb;   // FP32 masters and Adam moments
     std::vector<uint16_t*> Wbf, WbfT;           // BF16 copies (out x in) and (in x out)
-    int step = 0;
+    int step = 0;                               // Adam steps taken
+    int32_t* dstep = nullptr;                   // the same count on the device
     std::vector<void*> allocs;
 
     template <class T>
@@ -33,133 +34,169 @@ struct smdl_prop {
 
 namespace {
 
-inline int64_t pad32(int64_t x) { return (x + 31) / 32 * 32; }
+inline int64_t pad64b(int64_t x) { return (x + 63) / 64 * 64; }
 
-// Activation buffers for a batch of Bpad rows (h_0 .. h_{L-1} bf16, deltas, logits).
+// Activation buffers for a batch of Bpad rows (a multiple of 64).
 struct Acts {
-    std::vector<uint16_t*> h;      // h[l]: Bpad x widths[l]
-    float* logits = nullptr;       // Bpad x K
-    std::vector<float*> dF;        // deltas FP32: dF[l]: Bpad x widths[l+1]
-    std::vector<uint16_t*> dB;     // deltas BF16
-    double* loss_part = nullptr;
-    double* loss = nullptr;
-    uint16_t* tB = nullptr;        // transposed delta (widths x Bpad)
-    uint16_t* tH = nullptr;        // transposed activation (widths x Bpad)
+    int64_t Bpad = 0;
+    std::vector<uint16_t*> h;      // h[l]: Bpad x widths[l], input of layer l (BF16)
+    float* logits = nullptr;       // Bpad x K (inference)
+    // training only
+    std::vector<uint16_t*> hT;     // widths[l] x Bpad
+    std::vector<uint16_t*> d;      // d[l]: Bpad x widths[l + 1], BF16 delta at the output of layer l
+    std::vector<uint16_t*> dT;     // widths[l + 1] x Bpad
+    std::vector<float*> part;      // (Bpad / 32) x widths[l + 1] column sums of the FP32 deltas
 };
 
 smdl_status get_acts(smdl_t h, smdl_prop_t p, int64_t Bpad, bool train, Acts& a) {
     const int L = p->n_layers;
-    a.h.resize(L);
+    a.Bpad = Bpad;
+    a.h.assign(L, nullptr);
     for (int l = 0; l < L; ++l) {
         std::string nm = "prop.h" + std::to_string(l);
         a.h[l] = (uint16_t*)h->ws(nm.c_str(), (size_t)Bpad * p->widths[l] * 2);
         if (!a.h[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     }
-    a.logits = (float*)h->ws("prop.logits", (size_t)Bpad * p->widths[L] * 4);
-    if (!a.logits) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
-    if (train) {
-        a.dF.resize(L);
-        a.dB.resize(L);
-        for (int l = 0; l < L; ++l) {
-            std::string nf = "prop.dF" + std::to_string(l), nb = "prop.dB" + std::to_string(l);
-            a.dF[l] = (float*)h->ws(nf.c_str(), (size_t)Bpad * p->widths[l + 1] * 4);
-            a.dB[l] = (uint16_t*)h->ws(nb.c_str(), (size_t)Bpad * p->widths[l + 1] * 2);
-            if (!a.dF[l] || !a.dB[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
-        }
-        int wmax = 0;
-        for (int w : p->widths) wmax = std::max(wmax, w);
-        a.tB = (uint16_t*)h->ws("prop.tB", (size_t)Bpad * wmax * 2);
-        a.tH = (uint16_t*)h->ws("prop.tH", (size_t)Bpad * wmax * 2);
-        if (!a.tB || !a.tH) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
-        a.loss_part = (double*)h->ws("prop.lossp", (size_t)Bpad * 8);
-        a.loss = (double*)h->ws("prop.loss", 8);
-        if (!a.loss_part || !a.loss) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    if (!train) {
+        a.logits = (float*)h->ws("prop.logits", (size_t)Bpad * p->widths[L] * 4);
+        if (!a.logits) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+        return SMDL_OK;
+    }
+    a.hT.assign(L, nullptr);
+    a.d.assign(L, nullptr);
+    a.dT.assign(L, nullptr);
+    a.part.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+        const std::string k = std::to_string(l);
+        const int wi = p->widths[l], wo = p->widths[l + 1];
+        a.hT[l] = (uint16_t*)h->ws(("prop.hT" + k).c_str(), (size_t)Bpad * wi * 2);
+        a.d[l] = (uint16_t*)h->ws(("prop.d" + k).c_str(), (size_t)Bpad * wo * 2);
+        a.dT[l] = (uint16_t*)h->ws(("prop.dT" + k).c_str(), (size_t)Bpad * wo * 2);
+        a.part[l] = (float*)h->ws(("prop.part" + k).c_str(), (size_t)(Bpad / 32) * wo * 4);
+        if (!a.hT[l] || !a.d[l] || !a.dT[l] || !a.part[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     }
     return SMDL_OK;
 }
 
-// Forward pass over M rows (rows >= B of h_0 are zero).  logits_out: M x K FP32.
-hipError_t enqueue_forward(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, int64_t M,
-                           const int32_t* rows, Acts& a, float* logits_out) {
+// Forward pass over the B rows of Y (gathered through `rows` when set), padded to a.Bpad.
+// Inference: logits_out (B x K FP32).  Training (tmask set): the output layer applies the BCE
+// loss (added to *loss) and writes the output deltas; every layer input is also stored
+// transposed for the weight gradients.
+hipError_t enqueue_forward(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, const int32_t* rows, Acts& a,
+                           float* logits_out, const uint32_t* tmask, int tstride, double* loss) {
     const int L = p->n_layers;
-    const int m = p->widths[0];
-    hipError_t e = launch_prep_input(Y, B, m, m, M, rows, a.h[0], h->stream);
+    const bool train = tmask != nullptr;
+    const int64_t Bpad = a.Bpad;
+    hipError_t e = launch_prep(Y, B, p->widths[0], Bpad, rows, a.h[0], train ? a.hT[0] : nullptr, h->stream);
     if (e != hipSuccess) return e;
     for (int l = 0; l < L; ++l) {
-        GemmArgs g{};
+        const int wi = p->widths[l], wo = p->widths[l + 1];
+        NtArgs g{};
         g.A = a.h[l];
-        g.lda = p->widths[l];
+        g.lda = wi;
         g.B = p->Wbf[l];
-        g.ldb = p->widths[l];
-        g.M = (int)M;
-        g.N = p->widths[l + 1];
-        g.K = p->widths[l];
-        g.ldc = p->widths[l + 1];
+        g.ldb = wi;
+        g.M = (int)Bpad;
+        g.N = wo;
+        g.K = wi;
+        g.Mvalid = (int)B;
         g.bias = p->b[l];
+        g.ldo = wo;
+        g.ldt = (int)Bpad;
         if (l + 1 < L) {
             g.relu = 1;
             g.out_bf16 = a.h[l + 1];
+            if (train) g.outT = a.hT[l + 1];
+        } else if (train) {
+            g.tmask = tmask;
+            g.tstride = tstride;
+            g.rows = rows;
+            g.scale = 1.0f / ((float)B * wo);
+            g.loss = loss;
+            g.out_bf16 = a.d[l];
+            g.outT = a.dT[l];
+            g.colpart = a.part[l];
         } else {
             g.out_f32 = logits_out;
         }
-        e = launch_gemm(g, false, false, M >= 4096, h->stream);
-        if (e != hipSuccess) return e;
+        if ((e = launch_gemm_nt(g, h->stream)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// Loss and gradients for a batch (rows of Y / labels given by `rows`, or the first B).
-hipError_t enqueue_grad(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, const int32_t* rows,
-                        const smdl_codes& labels, Acts& a, float* const* dW, float* const* db) {
+// Backward pass after a training forward: the deltas of every layer (BF16, transposed, column
+// sums), then one grouped launch for all weight and bias gradients, applied with Adam when
+// `adam` is set (step t) or stored in dW / db.
+hipError_t enqueue_backward(smdl_t h, smdl_prop_t p, int64_t B, Acts& a, const smdl_train_opts* adam, int t_off,
+                            float* const* dW, float* const* db) {
     const int L = p->n_layers;
-    const int K = p->widths[L];
-    const int64_t Bpad = pad32(B);
-    hipError_t e = enqueue_forward(h, p, Y, B, Bpad, rows, a, a.logits);
-    if (e != hipSuccess) return e;
-    e = launch_bce(a.logits, B, Bpad, K, labels.idx, labels.nnz, labels.s_max, rows, 1.0f / ((float)B * K),
-                   a.dF[L - 1], a.dB[L - 1], a.loss_part, a.loss, h->stream);
-    if (e != hipSuccess) return e;
-    for (int l = L - 1; l >= 0; --l) {
-        // dW_l = delta_l^T h_l (M = out, N = in, K = Bpad): both operands transposed once through
-        // LDS, then the row-major GEMM with the batch split over blockIdx.z
-        const int wo = p->widths[l + 1], wi = p->widths[l];
-        if ((e = launch_transpose_bf16(a.dB[l], (int)Bpad, wo, a.tB, h->stream)) != hipSuccess) return e;
-        if ((e = launch_transpose_bf16(a.h[l], (int)Bpad, wi, a.tH, h->stream)) != hipSuccess) return e;
-        if ((e = launch_zero_f32(dW[l], (int64_t)wo * wi, h->stream)) != hipSuccess) return e;
-        GemmArgs g{};
-        g.A = a.tB;
-        g.lda = (int)Bpad;
-        g.B = a.tH;
-        g.ldb = (int)Bpad;
-        g.M = wo;
+    const int64_t Bpad = a.Bpad;
+    hipError_t e;
+    for (int l = L - 1; l >= 1; --l) {
+        // d_{l-1} = (d_l W_l) * [h_l > 0]
+        const int wi = p->widths[l], wo = p->widths[l + 1];
+        NtArgs g{};
+        g.A = a.d[l];
+        g.lda = wo;
+        g.B = p->WbfT[l];
+        g.ldb = wo;
+        g.M = (int)Bpad;
         g.N = wi;
-        g.K = (int)Bpad;
-        g.ldc = wi;
-        g.out_f32 = dW[l];
-        g.ksplit = 1;
-        const int tiles = ((wo + 63) / 64) * ((wi + 63) / 64);
-        while (g.ksplit < 8 && tiles * g.ksplit * 2 <= 512 && Bpad % (32 * g.ksplit * 2) == 0) g.ksplit *= 2;
-        if ((e = launch_gemm(g, false, false, false, h->stream)) != hipSuccess) return e;
-        if ((e = launch_colsum(a.dF[l], Bpad, wo, db[l], h->stream)) != hipSuccess) return e;
-        if (l > 0) {
-            // delta_{l-1} = (delta_l W_l) * [h_l > 0]   (M = Bpad, N = in, K = out)
-            GemmArgs q{};
-            q.A = a.dB[l];
-            q.lda = wo;
-            q.B = p->WbfT[l];
-            q.ldb = wo;
-            q.M = (int)Bpad;
-            q.N = wi;
-            q.K = wo;
-            q.ldc = wi;
-            q.mask_bf16 = a.h[l];
-            q.ldmask = wi;
-            q.out_f32 = a.dF[l - 1];
-            q.out_bf16 = a.dB[l - 1];
-            if ((e = launch_gemm(q, false, false, false, h->stream)) != hipSuccess) return e;
-        }
+        g.K = wo;
+        g.Mvalid = (int)B;
+        g.mask = a.h[l];
+        g.ldmask = wi;
+        g.out_bf16 = l - 1 >= 1 ? a.d[l - 1] : nullptr;
+        g.ldo = wi;
+        g.outT = a.dT[l - 1];
+        g.ldt = (int)Bpad;
+        g.colpart = a.part[l - 1];
+        if ((e = launch_gemm_nt(g, h->stream)) != hipSuccess) return e;
     }
-    return hipSuccess;
+    WgArgs w{};
+    w.n_layers = L;
+    w.Bpad = (int)Bpad;
+    w.adam = adam != nullptr;
+    if (adam) {
+        w.lr = adam->lr;
+        w.b1 = adam->beta1;
+        w.b2 = adam->beta2;
+        w.eps = adam->adam_eps;
+        w.t_dev = p->dstep;
+        w.t_off = t_off;
+    }
+    for (int l = 0; l < L; ++l) {
+        WgLayer& q = w.L[l];
+        q.dT = a.dT[l];
+        q.hT = a.hT[l];
+        q.colpart = a.part[l];
+        q.nparts = (int)(Bpad / 32);
+        q.wo = p->widths[l + 1];
+        q.wi = p->widths[l];
+        q.W = p->W[l];
+        q.b = p->b[l];
+        q.mW = p->mW[l];
+        q.vW = p->vW[l];
+        q.mb = p->mb[l];
+        q.vb = p->vb[l];
+        q.Wbf = p->Wbf[l];
+        q.WbfT = p->WbfT[l];
+        q.dW_out = dW ? dW[l] : nullptr;
+        q.db_out = db ? db[l] : nullptr;
+    }
+    return launch_wgrad(w, h->stream);
+}
+
+// Multi-hot label bitmask of N samples (workspace), rows of (K + 31) / 32 words.
+uint32_t* label_mask(smdl_t h, const smdl_codes& labels, int64_t N, int K, hipError_t& e) {
+    const int words = (K + 31) / 32;
+    uint32_t* m = (uint32_t*)h->ws("prop.tmask", (size_t)std::max<int64_t>(N, 1) * words * 4);
+    if (!m) {
+        e = hipErrorOutOfMemory;
+        return nullptr;
+    }
+    e = launch_label_mask(labels.idx, labels.nnz, labels.s_max, N, K, m, h->stream);
+    return m;
 }
 
 smdl_status check_prop(smdl_t h, smdl_prop_t p) {
@@ -188,6 +225,11 @@ extern "C" smdl_status smdl_prop_create(smdl_t h, int n_layers, const int* width
     p->h = h;
     p->n_layers = n_layers;
     p->widths.assign(widths, widths + n_layers + 1);
+    p->dstep = p->alloc<int32_t>(1);
+    if (!p->dstep || hipMemsetAsync(p->dstep, 0, 4, h->stream) != hipSuccess) {
+        smdl_prop_destroy(p);
+        return h->fail(SMDL_E_NOMEM, "proposer allocation failed");
+    }
     for (int l = 0; l < n_layers; ++l) {
         const size_t nw = (size_t)widths[l] * widths[l + 1], nb = widths[l + 1];
         float *W = p->alloc<float>(nw), *b = p->alloc<float>(nb);
@@ -261,8 +303,9 @@ extern "C" smdl_status smdl_prop_logits(smdl_t h, smdl_prop_t p, const float* Y,
     if (N > INT32_MAX / 4) return h->fail(SMDL_E_SHAPE, "N too large");
     (void)hipSetDevice(h->device);
     Acts a;
-    if ((st = get_acts(h, p, N, false, a)) != SMDL_OK) return st;
-    if ((st = h->hip(enqueue_forward(h, p, Y, N, N, nullptr, a, logits), "forward")) != SMDL_OK) return st;
+    if ((st = get_acts(h, p, pad64b(N), false, a)) != SMDL_OK) return st;
+    if ((st = h->hip(enqueue_forward(h, p, Y, N, nullptr, a, logits, nullptr, 0, nullptr), "forward")) != SMDL_OK)
+        return st;
     return h->hip(hipStreamSynchronize(h->stream), "forward");
 }
 
@@ -286,12 +329,21 @@ extern "C" smdl_status smdl_prop_grad(smdl_t h, smdl_prop_t p, const float* Y, i
         if (!dW[l] || !db[l]) return h->fail(SMDL_E_ARG, "null gradient array");
     (void)hipSetDevice(h->device);
     Acts a;
-    if ((st = get_acts(h, p, pad32(N), true, a)) != SMDL_OK) return st;
-    if ((st = h->hip(enqueue_grad(h, p, Y, N, nullptr, labels, a, dW, db), "grad")) != SMDL_OK) return st;
+    if ((st = get_acts(h, p, pad64b(N), true, a)) != SMDL_OK) return st;
+    const int K = p->widths[p->n_layers];
+    double* dloss = (double*)h->ws("prop.loss", 8);
+    if (!dloss) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    hipError_t e;
+    const uint32_t* tm = label_mask(h, labels, N, K, e);
+    if (e != hipSuccess) return h->hip(e, "labels");
+    if ((e = launch_zero_f64(dloss, 1, h->stream)) != hipSuccess) return h->hip(e, "grad");
+    if ((e = enqueue_forward(h, p, Y, N, nullptr, a, nullptr, tm, (K + 31) / 32, dloss)) != hipSuccess)
+        return h->hip(e, "grad");
+    if ((e = enqueue_backward(h, p, N, a, nullptr, 0, dW, db)) != hipSuccess) return h->hip(e, "grad");
     double l = 0.0;
-    if ((st = h->hip(hipMemcpyAsync(&l, a.loss, 8, hipMemcpyDeviceToHost, h->stream), "loss")) != SMDL_OK) return st;
+    if ((st = h->hip(hipMemcpyAsync(&l, dloss, 8, hipMemcpyDeviceToHost, h->stream), "loss")) != SMDL_OK) return st;
     if ((st = h->hip(hipStreamSynchronize(h->stream), "grad")) != SMDL_OK) return st;
-    if (loss) *loss = (float)(l / ((double)N * p->widths[p->n_layers]));
+    if (loss) *loss = (float)(l / ((double)N * K));
     return SMDL_OK;
 }
 
@@ -308,21 +360,17 @@ extern "C" smdl_status smdl_prop_train(smdl_t h, smdl_prop_t p, const float* Y, 
     if ((st = check_labels(h, labels, N)) != SMDL_OK) return st;
     if (N > INT32_MAX / 8) return h->fail(SMDL_E_SHAPE, "N too large");
     (void)hipSetDevice(h->device);
-    const int L = p->n_layers;
     const int64_t B = o->batch;
     const int64_t nb = N / B;
+    const int K = p->widths[p->n_layers];
     Acts a;
-    if ((st = get_acts(h, p, pad32(B), true, a)) != SMDL_OK) return st;
-    std::vector<float*> gW(L), gb(L);
-    for (int l = 0; l < L; ++l) {
-        std::string n1 = "prop.gW" + std::to_string(l), n2 = "prop.gb" + std::to_string(l);
-        gW[l] = (float*)h->ws(n1.c_str(), (size_t)p->widths[l] * p->widths[l + 1] * 4);
-        gb[l] = (float*)h->ws(n2.c_str(), (size_t)p->widths[l + 1] * 4);
-        if (!gW[l] || !gb[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
-    }
+    if ((st = get_acts(h, p, pad64b(B), true, a)) != SMDL_OK) return st;
     int32_t* rows = (int32_t*)h->ws("prop.rows", (size_t)std::max<int64_t>(N, 1) * 4);
-    double* eloss = (double*)h->ws("prop.eloss", 8 * (size_t)std::max(1, nb > 0 ? (int)nb : 1));
+    double* eloss = (double*)h->ws("prop.eloss", 8 * (size_t)std::max<int64_t>(nb, 1));
     if (!rows || !eloss) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    hipError_t e;
+    const uint32_t* tm = label_mask(h, labels, N, K, e);
+    if (e != hipSuccess) return h->hip(e, "labels");
     std::vector<int32_t> order(N);
     std::iota(order.begin(), order.end(), 0);
     uint64_t rng = o->shuffle_seed;
@@ -332,39 +380,79 @@ extern "C" smdl_status smdl_prop_train(smdl_t h, smdl_prop_t p, const float* Y, 
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
         return z ^ (z >> 31);
     };
-    const int K = p->widths[L];
+    // One epoch (every Adam step over the batches of `rows`) is captured once as a graph and
+    // replayed per epoch; the shuffled order is copied into `rows` before each replay and the
+    // Adam step count lives on the device.
+    auto one_epoch = [&]() -> hipError_t {
+        hipError_t e2 = launch_zero_f64(eloss, std::max<int64_t>(nb, 1), h->stream);
+        for (int64_t bi = 0; bi < nb && e2 == hipSuccess; ++bi) {
+            e2 = enqueue_forward(h, p, Y, B, rows + bi * B, a, nullptr, tm, (K + 31) / 32, eloss + bi);
+            if (e2 == hipSuccess) e2 = enqueue_backward(h, p, B, a, o, (int)bi + 1, nullptr, nullptr);
+        }
+        if (e2 == hipSuccess) e2 = launch_add_i32(p->dstep, (int32_t)nb, h->stream);
+        return e2;
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (o->epochs > 0 && nb > 0) {
+        if ((st = h->hip(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "capture")) != SMDL_OK)
+            return st;
+        e = one_epoch();
+        hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return h->hip(e != hipSuccess ? e : e2, "capture");
+        }
+        if ((st = h->hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate")) != SMDL_OK) {
+            (void)hipGraphDestroy(graph);
+            return st;
+        }
+    }
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(h->stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    };
+    // each epoch's order gets its own host buffer, alive until the end, so that the queued copies
+    // never read a buffer the next shuffle rewrites (beyond 2^26 entries: one buffer and a
+    // synchronisation per epoch instead)
+    const bool keep_all = (int64_t)o->epochs * N <= (int64_t)1 << 26;
+    std::vector<std::vector<int32_t>> orders;
     for (int ep = 0; ep < o->epochs; ++ep) {
         if (o->shuffle_seed) {
             for (int64_t i = N - 1; i > 0; --i) std::swap(order[i], order[next() % (uint64_t)(i + 1)]);
         }
-        if ((st = h->hip(hipMemcpyAsync(rows, order.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream), "rows")) != SMDL_OK)
-            return st;
-        for (int64_t bi = 0; bi < nb; ++bi) {
-            hipError_t e = enqueue_grad(h, p, Y, B, rows + bi * B, labels, a, gW.data(), gb.data());
-            if (e != hipSuccess) return h->hip(e, "train step");
-            if ((e = hipMemcpyAsync(eloss + bi, a.loss, 8, hipMemcpyDeviceToDevice, h->stream)) != hipSuccess)
-                return h->hip(e, "loss");
-            ++p->step;
-            for (int l = 0; l < L; ++l) {
-                const int64_t nw = (int64_t)p->widths[l] * p->widths[l + 1];
-                e = launch_adam(p->W[l], gW[l], p->mW[l], p->vW[l], nw, p->widths[l], p->widths[l + 1], o->lr, o->beta1,
-                                o->beta2, o->adam_eps, p->step, p->Wbf[l], p->WbfT[l], h->stream);
-                if (e == hipSuccess)
-                    e = launch_adam(p->b[l], gb[l], p->mb[l], p->vb[l], p->widths[l + 1], p->widths[l + 1], 1, o->lr,
-                                    o->beta1, o->beta2, o->adam_eps, p->step, nullptr, nullptr, h->stream);
-                if (e != hipSuccess) return h->hip(e, "adam");
+        if (nb > 0) {
+            if (keep_all) {
+                orders.push_back(order);
+            } else if (ep > 0 && (st = h->hip(hipStreamSynchronize(h->stream), "train")) != SMDL_OK) {
+                cleanup();
+                return st;
             }
+            const int32_t* src = keep_all ? orders.back().data() : order.data();
+            if ((st = h->hip(hipMemcpyAsync(rows, src, (size_t)N * 4, hipMemcpyHostToDevice, h->stream), "rows")) != SMDL_OK ||
+                (st = h->hip(hipGraphLaunch(exec, h->stream), "graph launch")) != SMDL_OK) {
+                cleanup();
+                return st;
+            }
+            p->step += (int)nb;
         }
         if (loss_per_epoch) {
             std::vector<double> el(std::max<int64_t>(nb, 1));
-            if (nb > 0 && (st = h->hip(hipMemcpyAsync(el.data(), eloss, nb * 8, hipMemcpyDeviceToHost, h->stream), "loss")) != SMDL_OK)
+            if (nb > 0 && (st = h->hip(hipMemcpyAsync(el.data(), eloss, nb * 8, hipMemcpyDeviceToHost, h->stream), "loss")) != SMDL_OK) {
+                cleanup();
                 return st;
-            if ((st = h->hip(hipStreamSynchronize(h->stream), "train")) != SMDL_OK) return st;
+            }
+            if ((st = h->hip(hipStreamSynchronize(h->stream), "train")) != SMDL_OK) {
+                cleanup();
+                return st;
+            }
             double s = 0.0;
             for (int64_t i = 0; i < nb; ++i) s += el[i] / ((double)B * K);
             loss_per_epoch[ep] = nb > 0 ? (float)(s / nb) : 0.f;
         }
     }
+    cleanup();
     return h->hip(hipStreamSynchronize(h->stream), "train");
 }
 
@@ -388,14 +476,15 @@ extern "C" smdl_status smdl_omp_code_proposed(smdl_t h, smdl_prop_t p, const flo
     if (N > INT32_MAX / 64) return h->fail(SMDL_E_SHAPE, "N too large");
     (void)hipSetDevice(h->device);
     Acts a;
-    if ((st = get_acts(h, p, N, false, a)) != SMDL_OK) return st;
+    if ((st = get_acts(h, p, pad64b(N), false, a)) != SMDL_OK) return st;
     int32_t* cand = cand_out ? cand_out : (int32_t*)h->ws("prop.cand", (size_t)N * n_cand * 4);
     int32_t* fb_list = (int32_t*)h->ws("prop.fbl", (size_t)N * 4);
     int32_t* fb_cnt = (int32_t*)h->ws("prop.fbc", 64);
     if (!cand || !fb_list || !fb_cnt) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     hipError_t e;
     (void)hipEventRecord(h->ev_prop[0], h->stream);
-    if ((e = enqueue_forward(h, p, Y, N, N, nullptr, a, a.logits)) != hipSuccess) return h->hip(e, "forward");
+    if ((e = enqueue_forward(h, p, Y, N, nullptr, a, a.logits, nullptr, 0, nullptr)) != hipSuccess)
+        return h->hip(e, "forward");
     if ((e = launch_topk(a.logits, N, K, n_cand, cand, h->stream)) != hipSuccess) return h->hip(e, "topk");
     (void)hipEventRecord(h->ev_prop[1], h->stream);
     // dictionary fragments and Gram for the restricted kernel and the fallback

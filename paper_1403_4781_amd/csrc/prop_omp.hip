@@ -1,8 +1,7 @@
 // Candidate selection and proposer-restricted OMP.
 //
-// topk: 16 lanes per signal; n_cand rounds of a group argmax over the logits (larger logit
-//   first, lower atom index on equal logits); the chosen atoms are written in increasing atom
-//   order.
+// topk: 16 lanes per signal; the n_cand largest logits (lower atom index on equal logits) by a
+//   bisection on order-preserving keys; the chosen atoms are written in increasing atom order.
 // restricted_omp: one group of 16 lanes per signal.  OMP on the candidate columns only:
 //   alpha_C = D_C^T y by gathered dot products, the same correlation-space progressive
 //   inverse-Cholesky steps as the full kernel with rows of G gathered at the candidates, then
@@ -18,23 +17,73 @@ constexpr int MAXC = 64;        // candidates per signal
 constexpr int GR = 16;          // lanes per signal
 constexpr int EC = MAXC / GR;   // candidate entries per lane
 
-// Top-n_cand selection: 16 lanes per signal (4 signals per wave).  Lane g holds the logits
-// of atoms g, g+16, ... (up to 64 of them for K <= 1024); every round takes the best head over
-// the 16 lanes (DPP butterfly inside the row: larger logit, lower atom on ties) and the owner
-// advances past it.  The chosen atoms are then written in increasing atom order.
-__device__ __forceinline__ void tk_combine(float& bv, int& bi, float ov, int oi) {
-    const bool take = (ov > bv) | ((ov == bv) & (oi < bi));
-    bv = take ? ov : bv;
-    bi = take ? oi : bi;
-}
-template <int CTRL>
-__device__ __forceinline__ void tk_dpp(float& bv, int& bi) {
-    const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(bv), CTRL, 0xf, 0xf, false));
-    const int oi = __builtin_amdgcn_mov_dpp(bi, CTRL, 0xf, 0xf, false);
-    tk_combine(bv, bi, ov, oi);
+// Top-n_cand selection, 16 lanes per signal (4 signals per wave); lane g holds the logits of
+// atoms g + 16 t (t < E).  Logits become order-preserving 32-bit keys (NaN ranks last); a
+// bisection over the key bits finds the n_cand-th largest key T (32 rounds of one group
+// count); the keys above T are taken, and of the keys equal to T the lowest atoms.  As atom
+// 16 t + g orders like (t, g), every lane writes its chosen atoms straight to their positions
+// in increasing atom order (group ballots and popcounts).
+// NaN ranks below every number (key 1); key 0 marks padding entries, which are never chosen
+// because at least K >= n_cand keys are >= 1.
+__device__ __forceinline__ uint32_t order_key(float x) {
+    if (x != x) return 1u;
+    const uint32_t u = __float_as_uint(x);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-constexpr int TKE = SMDL_MAX_K / 16;   // logits per lane
+__device__ __forceinline__ int group_isum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
+    return v;
+}
+
+// 16-bit mask of the lanes of this lane's group for which pred holds.
+__device__ __forceinline__ uint32_t group_ballot(bool pred, int grp) {
+    const uint64_t m = __ballot(pred);
+    return (uint32_t)(m >> (16 * grp)) & 0xffffu;
+}
+
+template <int E>
+__global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ logits, int64_t N, int K,
+                                                   int n_cand, int32_t* __restrict__ cand) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane & 15, grp = lane >> 4;
+    const int64_t n = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool valid = n < N;
+    uint32_t key[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int k = g + 16 * t;
+        key[t] = (valid && k < K) ? order_key(logits[n * K + k]) : 0u;   // 0: never chosen
+    }
+    // T = the largest threshold with at least n_cand keys >= T
+    uint32_t T = 0u;
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t T2 = T | (1u << b);
+        int c = 0;
+#pragma unroll
+        for (int t = 0; t < E; ++t) c += key[t] >= T2 ? 1 : 0;
+        T = group_isum(c) >= n_cand ? T2 : T;
+    }
+    int gt = 0;
+#pragma unroll
+    for (int t = 0; t < E; ++t) gt += key[t] > T ? 1 : 0;
+    const int need = n_cand - group_isum(gt);      // keys equal to T to take, lowest atoms first
+    const uint32_t below = (1u << g) - 1u;
+    int eq_before = 0, sel_before = 0;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const bool eq = key[t] == T;
+        const uint32_t em = group_ballot(eq, grp);
+        const bool take = key[t] > T || (eq && eq_before + __popc(em & below) < need);
+        const uint32_t sm = group_ballot(take, grp);
+        if (valid && take) cand[n * n_cand + sel_before + __popc(sm & below)] = g + 16 * t;
+        eq_before += __popc(em);
+        sel_before += __popc(sm);
+    }
+}
 
 // (|value| larger, then lower candidate position) combine for the restricted argmax.
 template <int CTRL>
@@ -45,62 +94,6 @@ __device__ __forceinline__ void ro_dpp(float& bv, int& bp) {
     const bool take = (ao > ab) | ((ao == ab) & (op < bp));
     bv = take ? ov : bv;
     bp = take ? op : bp;
-}
-
-__global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ logits, int64_t N, int K,
-                                                   int n_cand, int32_t* __restrict__ cand) {
-    __shared__ unsigned int chosen[16][SMDL_MAX_K / 32];
-    const int lane = threadIdx.x & 63;
-    const int g = lane & 15;
-    const int slot = threadIdx.x >> 4;
-    const int64_t n = (int64_t)blockIdx.x * 16 + slot;
-    const bool valid = n < N;
-    for (int w = g; w < SMDL_MAX_K / 32; w += 16) chosen[slot][w] = 0u;
-    const int E = (K + 15) / 16;
-    float v[TKE];
-    bool used[TKE];
-#pragma unroll
-    for (int t = 0; t < TKE; ++t) {
-        const int k = g + 16 * t;
-        const bool ok = valid && t < E && k < K;
-        float x = ok ? logits[n * K + k] : -INFINITY;
-        if (x != x) x = -INFINITY;          // NaN logits rank last
-        v[t] = x;
-        used[t] = !ok;
-    }
-    __syncthreads();
-    for (int c = 0; c < n_cand; ++c) {
-        // this lane's best unused entry
-        float bv = -INFINITY;
-        int bi = 0x7fffffff;
-#pragma unroll
-        for (int t = 0; t < TKE; ++t) {
-            const int k = g + 16 * t;
-            if (t < E && !used[t] && (v[t] > bv || (v[t] == bv && k < bi))) { bv = v[t]; bi = k; }
-        }
-        tk_dpp<0xB1>(bv, bi);
-        tk_dpp<0x4E>(bv, bi);
-        tk_dpp<0x141>(bv, bi);
-        tk_dpp<0x140>(bv, bi);
-#pragma unroll
-        for (int t = 0; t < TKE; ++t)
-            if (g + 16 * t == bi) used[t] = true;
-        if (g == 0 && valid && bi < K) chosen[slot][bi >> 5] |= 1u << (bi & 31);
-    }
-    __syncthreads();
-    if (!valid) return;
-    // increasing atom order: prefix counts over the bitmask words
-    if (g == 0) {
-        int pos = 0;
-        for (int w = 0; w < (K + 31) / 32 && pos < n_cand; ++w) {
-            unsigned int bits = chosen[slot][w];
-            while (bits && pos < n_cand) {
-                const int b = __ffs(bits) - 1;
-                bits &= bits - 1;
-                cand[n * n_cand + pos++] = 32 * w + b;
-            }
-        }
-    }
 }
 
 template <int SM>
@@ -296,7 +289,14 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
 }  // namespace
 
 hipError_t launch_topk(const float* logits, int64_t N, int K, int n_cand, int32_t* cand, hipStream_t st) {
-    hipLaunchKernelGGL(topk_kernel, dim3((unsigned)((N + 15) / 16)), dim3(256), 0, st, logits, N, K, n_cand, cand);
+    if (K < 1 || K > SMDL_MAX_K || n_cand < 1 || n_cand > K) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((N + 15) / 16));
+    const int E = (K + 15) / 16;
+    if (E <= 4) hipLaunchKernelGGL(topk_kernel<4>, grid, dim3(256), 0, st, logits, N, K, n_cand, cand);
+    else if (E <= 8) hipLaunchKernelGGL(topk_kernel<8>, grid, dim3(256), 0, st, logits, N, K, n_cand, cand);
+    else if (E <= 16) hipLaunchKernelGGL(topk_kernel<16>, grid, dim3(256), 0, st, logits, N, K, n_cand, cand);
+    else if (E <= 32) hipLaunchKernelGGL(topk_kernel<32>, grid, dim3(256), 0, st, logits, N, K, n_cand, cand);
+    else hipLaunchKernelGGL(topk_kernel<64>, grid, dim3(256), 0, st, logits, N, K, n_cand, cand);
     return hipGetLastError();
 }
 
