@@ -69,7 +69,7 @@ def cpu_baseline(w, sample_subsets: int, sample_n: int, iters: int):
     oracle.split_merge(Ys, perm, offs, [256] * sample_subsets, [8] * sample_subsets, 256, iters, iters, 4, 8)
     dt = time.perf_counter() - t0
     codings = sample_subsets * sample_n * (iters + 1) + len(idx)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.threads()
     return {"value": codings / dt, "unit": "signals sparse-coded/sec (m=64,K=256,s=8)", "cores": threads,
             "kind": "oracle",
             "sample": f"Algorithm 1 on {sample_subsets} subsets x {sample_n} signals of the same data, "
@@ -84,9 +84,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-subsets", type=int, default=2)
+    ap.add_argument("--cpu-subsets", type=int, default=16)
     ap.add_argument("--cpu-n", type=int, default=5000)
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--omp-only", type=int, default=0,
                     help="only run the plain OMP coding of the 100000 signals this many times (for profilers)")
     ap.add_argument("--copy-calib", type=int, default=0,

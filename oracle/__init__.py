@@ -53,6 +53,7 @@ def lib():
                                       C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                       dp, ip, dp, ip, dp, dp]
         L.ora_set_bf16.argtypes = [C.c_int]
+        L.ora_threads.restype = C.c_int
         L.ora_bf16.argtypes = [C.c_double]
         L.ora_bf16.restype = C.c_double
         L.ora_mlp_forward.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(dp), C.POINTER(dp), dp,
@@ -168,6 +169,11 @@ def split_merge(Y, perm, offsets, K_local, s_local, K, iters_local, iters_merge,
     if rc != 0:
         raise FloatingPointError(f"oracle split-merge failed ({rc})")
     return D, (Codes(idx, coef, nnz) if codes else None), Dl, sc
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(lib().ora_threads())
 
 
 def set_bf16_rounding(enabled: bool) -> None:

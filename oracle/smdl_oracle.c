@@ -25,6 +25,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_OK 0
 #define ORA_E_ARG (-1)
@@ -617,4 +620,13 @@ int ora_propose_code(const double* D, int m, int K, const double* Y, int64_t N,
         free(cand); free(taken); free(Dc); free(work); free(ix); free(cf); free(r);
     }
     return ORA_OK;
+}
+
+/* Threads the OpenMP loops of this library use (1 without OpenMP). */
+int ora_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
