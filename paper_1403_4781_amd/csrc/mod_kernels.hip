@@ -6,11 +6,12 @@
 //  2. mod_products: one block per atom a: column a of A = X X^T (FP64, LDS) and column a of
 //     B = Y X^T (FP64 register accumulation over the atom's list), written below each other as
 //     column a of the augmented matrix M = [A; B] ((Kpad + m) x Kpad, FP64).
-//  3. chol_factor: one block per dictionary: blocked FP64 Cholesky of A (MFMA trailing updates),
-//     a ridge retry when a pivot is rejected.  Atoms no signal uses get an identity diagonal
-//     (their column of A is zero) and keep their value.
-//  4. tri_solve: D A = B row by row (forward then backward substitution), many blocks per
-//     dictionary; mod_normalize: unit normalisation of the solved atoms.
+//  3. chol_factor: one block per dictionary: blocked FP64 Cholesky of A with the B rows carried
+//     along (they end as Z = B L^{-T}), MFMA trailing updates, a ridge retry when a pivot is
+//     rejected.  Atoms no signal uses get an identity diagonal (their column of A is zero) and
+//     keep their value.
+//  4. tri_solve: D L = Z by block columns (MFMA products, small triangular blocks), one block
+//     per dictionary; mod_normalize: unit normalisation of the solved atoms.
 #include "smdl_internal.h"
 
 namespace {
@@ -148,25 +149,41 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
 }
 
 // ------------------------------------------------------------------------------------------
-// FP64 Cholesky factorisation of A (one block per dictionary)
+// FP64 Cholesky factorisation of the augmented matrix [A; B] (one block per dictionary)
 // ------------------------------------------------------------------------------------------
 // status[8*t + 0] = unused atoms (this call), [1] |= ridge used, [2] |= failed, [3] |= bad codes,
 // [4] = failed in this call (read by the solve and normalisation kernels).  The caller zeroes
 // the status array before a sequence of updates.
 //
-// Right-looking, panel width FB = 32:
-//   (i)   the 32 x 32 diagonal block is factored by one wave with one row per lane in registers,
-//         column values broadcast with readlane;
-//   (ii)  the rows below it are solved against it (one row per thread, L_kk in LDS);
-//   (iii) the trailing lower triangle is updated on the FP64 matrix cores (16 x 16 tiles,
-//         v_mfma_f64_16x16x4f64), the panel read from LDS when it fits.
-// Finally L is mirrored into the upper triangle (W[i*ld + j] = L[i][j]) so that the backward
-// substitution reads rows of L contiguously.
-constexpr int FB = 32;
+// W (column-major, ld = Kpad + m) holds [A; B]; A = L L^T is factored in place and the B rows are
+// carried along as extra rows of every panel, so that they end as Z = B L^{-T} (the forward half
+// of D A = B).  Right-looking, panel width FB = 16 (the unrolled register factorisation of a
+// 32-wide diagonal block does not fit in a 512-thread block's registers):
+//   (i)   the 16 x 16 diagonal block: one row per lane of wave 0, each finished column broadcast
+//         through LDS; the reciprocals of the diagonal are kept;
+//   (ii)  every row below it (A rows and B rows) solves x L_kk^T = w right-looking (depth 16,
+//         no divisions); A rows are also written transposed (W[i*ld + j] = L[i][j], j < i),
+//         which the backward substitution reads contiguously;
+//   (iii) the trailing lower triangle of A and the trailing B rows are updated on the FP64
+//         matrix cores (v_mfma_f64_16x16x4f64, 16 x 16 tiles, the panel from LDS when it fits),
+//         oriented so that consecutive lanes touch consecutive rows of W; each wave takes its
+//         tiles four at a time with all their old values requested first.
+constexpr int FB = 16;
 constexpr int CT = 512;
-constexpr int PR = 480;                      // panel rows kept in LDS (32 x 480 doubles = 120 KB)
+constexpr int PR = 1168;                     // panel rows kept in LDS (16 x 1168 doubles = 146 KB);
+                                             // 1168 = 16 mod 32 puts the four k-groups of an MFMA
+                                             // operand read on alternating halves of the banks
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// FP64 global accesses at a 32-bit byte offset from a uniform base (W stays below 4 GiB: Kpad,
+// m <= 1024 + 256): one VGPR per address instead of a 64-bit pair.
+__device__ __forceinline__ double gld(const double* base, uint32_t off) {
+    return *(const __attribute__((address_space(1))) double*)(reinterpret_cast<const char*>(base) + off);
+}
+__device__ __forceinline__ void gst(double* base, uint32_t off, double v) {
+    *(__attribute__((address_space(1))) double*)(reinterpret_cast<char*>(base) + off) = v;
+}
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const long long b = __double_as_longlong(v);
@@ -183,8 +200,10 @@ __global__ __launch_bounds__(CT) void chol_factor_kernel(const ModDesc* __restri
     const int ld = Kp + m;
     const double* P = d.A;
     double* W = d.W;
-    __shared__ double Ld[FB][FB + 1];
-    __shared__ double panel[FB * PR];        // panel[c * PR + row]
+    __shared__ double LdT[FB][FB + 1];       // LdT[c][r] = L[kb + r][kb + c]
+    __shared__ double rdiag[FB];             // 1 / L[kb + c][kb + c]
+    __shared__ double colb[FB];              // column broadcast of the diagonal factorisation
+    __shared__ double panel[FB * PR];        // panel[c * PR + row - r0]
     __shared__ double diag0[SMDL_MAX_K];
     __shared__ unsigned char active[SMDL_MAX_K];
     __shared__ int s_fail, s_failed_final;
@@ -227,26 +246,47 @@ __global__ __launch_bounds__(CT) void chol_factor_kernel(const ModDesc* __restri
 
     for (int attempt = 0; attempt < 2; ++attempt) {
         const double lam = attempt == 0 ? 0.0 : RIDGE * maxdiag;
-        // W[0:Kp, 0:Kp] = A (+ lam I on active atoms, identity on unused ones)
-        const int total = Kp * Kp;
-#pragma unroll 4
-        for (int f = tid; f < total; f += CT) {
-            const int col = f / Kp, row = f - col * Kp;
-            double v = P[(int64_t)col * ld + row];
-            if (row == col) v = active[col] ? v + lam : 1.0;
-            W[(int64_t)col * ld + row] = v;
+        // W = [A (+ lam I on active atoms, identity diagonal on unused ones); B], sixteen loads
+        // in flight per thread
+        const int total = Kp * ld;
+        for (int f0 = tid; f0 < total; f0 += 16 * CT) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int f = f0 + u * CT;
+                v[u] = f < total ? P[f] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int f = f0 + u * CT;
+                if (f < total) {
+                    const int col = f / ld, row = f - col * ld;
+                    double x = v[u];
+                    if (row == col) x = active[col] ? x + lam : 1.0;
+                    W[f] = x;
+                }
+            }
         }
         for (int a = tid; a < Kp; a += CT) diag0[a] = active[a] ? P[(int64_t)a * ld + a] + lam : 1.0;
         if (tid == 0) s_fail = 0;
         __syncthreads();
 
         for (int kb = 0; kb < Kp; kb += FB) {
-            // (i) diagonal block: lane i < FB holds row i in registers
+            // (i) diagonal block, staged through LdT (LdT[c][r] = block entry (r, c), r >= c);
+            // lane i < FB of wave 0 holds row i in registers
+            for (int f = tid; f < FB * FB; f += CT) {
+                const int c = f / FB, r = f % FB;
+                LdT[c][r] = r >= c ? gld(W, 8u * (uint32_t)((kb + c) * ld + kb + r)) : 0.0;
+            }
+            __syncthreads();
             if (wave == 0) {
+                // Entries above a row's diagonal (c > lane) are don't-care values: updating them
+                // unconditionally avoids one lane mask per column; they are never read.  Lanes
+                // FB..63 repeat lanes 0..FB-1.
+                const int li = lane & (FB - 1);
                 double a[FB];
 #pragma unroll
-                for (int c = 0; c < FB; ++c)
-                    a[c] = (lane < FB && c <= lane) ? W[(int64_t)(kb + c) * ld + kb + lane] : 0.0;
+                for (int c = 0; c < FB; ++c) a[c] = LdT[c][li];
                 bool bad = false;
 #pragma unroll
                 for (int j = 0; j < FB; ++j) {
@@ -255,79 +295,116 @@ __global__ __launch_bounds__(CT) void chol_factor_kernel(const ModDesc* __restri
                     bad |= b;
                     const double dj = b ? 1.0 : sqrt(djj);
                     const double rd = 1.0 / dj;
-                    a[j] = (lane == j) ? dj : (lane > j ? a[j] * rd : a[j]);
+                    a[j] *= rd;                           // lane j: d_j; lanes i > j: L[i][j]
+                    colb[li] = a[j];
+                    if (lane == 0) rdiag[j] = rd;
 #pragma unroll
-                    for (int c = j + 1; c < FB; ++c) {
-                        const double lc = readlane_f64(a[j], c);   // L[c][j]
-                        if (lane >= c) a[c] = fma(-a[j], lc, a[c]);
-                    }
+                    for (int c = j + 1; c < FB; ++c) a[c] = fma(-a[j], colb[c], a[c]);
                 }
                 if (lane == 0 && bad) s_fail = 1;
                 if (lane < FB) {
 #pragma unroll
-                    for (int c = 0; c < FB; ++c) {
-                        Ld[lane][c] = c <= lane ? a[c] : 0.0;
-                        if (c <= lane) W[(int64_t)(kb + c) * ld + kb + lane] = a[c];
-                    }
+                    for (int c = 0; c < FB; ++c) LdT[c][lane] = a[c];
                 }
             }
             __syncthreads();
+            // the factored block back to W: column kb + c gets L[., kb + c] below the diagonal
+            // and, above it, the mirror W[i*ld + j] = L[i][j] (j < i) of row kb + c
+            for (int f = tid; f < FB * FB; f += CT) {
+                const int c = f / FB, r = f % FB;
+                gst(W, 8u * (uint32_t)((kb + c) * ld + kb + r), r >= c ? LdT[c][r] : LdT[r][c]);
+            }
+            __syncthreads();
             if (s_fail) break;
-            // (ii) panel rows below the block: x L_kk^T = w
+            // (ii) rows below the block (the rest of A, then B): x L_kk^T = w
             const int r0 = kb + FB;
-            const int R = Kp - r0;
-            const bool in_lds = R <= PR;
+            const int R = ld - r0;
+            const bool in_lds = (R + 15) / 16 * 16 <= PR;
             for (int rr = tid; rr < R; rr += CT) {
                 const int i = r0 + rr;
                 double x[FB];
 #pragma unroll
-                for (int c = 0; c < FB; ++c) x[c] = W[(int64_t)(kb + c) * ld + i];
+                for (int c = 0; c < FB; ++c) x[c] = gld(W, 8u * (uint32_t)((kb + c) * ld + i));
 #pragma unroll
                 for (int c = 0; c < FB; ++c) {
-                    double sacc = x[c];
+                    x[c] *= rdiag[c];
 #pragma unroll
-                    for (int cc = 0; cc < c; ++cc) sacc -= x[cc] * Ld[c][cc];
-                    x[c] = sacc / Ld[c][c];
-                    __asm__ volatile("" ::: "memory");     // keep the LDS reads of row c here
+                    for (int c2 = c + 1; c2 < FB; ++c2) x[c2] = fma(-x[c], LdT[c][c2], x[c2]);
+                    __asm__ volatile("" ::: "memory");     // keep column c's LDS reads in this step
                 }
 #pragma unroll
-                for (int c = 0; c < FB; ++c) W[(int64_t)(kb + c) * ld + i] = x[c];
+                for (int c = 0; c < FB; ++c) gst(W, 8u * (uint32_t)((kb + c) * ld + i), x[c]);
+                if (i < Kp) {
+#pragma unroll
+                    for (int c = 0; c < FB; ++c) gst(W, 8u * (uint32_t)(i * ld + kb + c), x[c]);   // mirror
+                }
                 if (in_lds) {
 #pragma unroll
                     for (int c = 0; c < FB; ++c) panel[c * PR + rr] = x[c];
                 }
             }
             __syncthreads();
-            // (iii) trailing update of the lower triangle: 16 x 16 tiles (ib >= jb) on MFMA
-            const int T16 = R / 16;                      // R is a multiple of 32
-            const int ntile = T16 * (T16 + 1) / 2;
-            for (int t = wave; t < ntile; t += CT / 64) {
-                // t -> (ib, jb), ib >= jb, enumerated row by row
-                int ib = (int)((sqrtf(8.f * t + 1.f) - 1.f) * 0.5f);
-                while ((ib + 1) * (ib + 2) / 2 <= t) ++ib;
-                while (ib * (ib + 1) / 2 > t) --ib;
-                const int jb = t - ib * (ib + 1) / 2;
-                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-                const int ri = 16 * ib + (lane & 15), rj = 16 * jb + (lane & 15), kq = lane >> 4;
+            // (iii) trailing update: lower triangle of the A block (tiles ib >= jb) and the B rows
+            // (tiles ib >= TA), T[row][col] -= sum_k X[row][k] X[col][k] over the panel columns
+            const int TA = (Kp - r0) / 16;
+            const int TBR = (m + 15) / 16;
+            const int nA = TA * (TA + 1) / 2;
+            const int ntile = nA + TBR * TA;
+            constexpr int NB4 = 4;
+            for (int t0 = wave; t0 < ntile; t0 += NB4 * (CT / 64)) {
+                int ibs[NB4], jbs[NB4];
+                bool okt[NB4], rv[NB4];
+                double old[NB4][4];
 #pragma unroll
-                for (int kc = 0; kc < FB; kc += 4) {
-                    double av, bv;
-                    if (in_lds) {
-                        av = panel[(kc + kq) * PR + ri];
-                        bv = panel[(kc + kq) * PR + rj];
-                    } else {
-                        av = W[(int64_t)(kb + kc + kq) * ld + r0 + ri];
-                        bv = W[(int64_t)(kb + kc + kq) * ld + r0 + rj];
+                for (int u = 0; u < NB4; ++u) {
+                    const int t = t0 + u * (CT / 64);
+                    okt[u] = t < ntile;
+                    int ib = 0, jb = 0;
+                    if (okt[u] && t < nA) {
+                        ib = (int)((sqrtf(8.f * t + 1.f) - 1.f) * 0.5f);
+                        while ((ib + 1) * (ib + 2) / 2 <= t) ++ib;
+                        while (ib * (ib + 1) / 2 > t) --ib;
+                        jb = t - ib * (ib + 1) / 2;
+                    } else if (okt[u]) {
+                        ib = TA + (t - nA) / TA;
+                        jb = (t - nA) % TA;
                     }
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-                }
-                // FP64 16x16x4 output: D[i][j] sits in lane j + 16 (i % 4), register i / 4, so
-                // acc[q] = sum_k X[16 ib + kq + 4 q][k] X[16 jb + (lane & 15)][k]
-                const int col = r0 + 16 * jb + (lane & 15);
+                    ibs[u] = ib;
+                    jbs[u] = jb;
+                    const int row = r0 + 16 * ib + (lane & 15);
+                    const int col = r0 + 16 * jb + (lane >> 4);
+                    rv[u] = okt[u] && row < ld;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = r0 + 16 * ib + kq + 4 * q;
-                    W[(int64_t)col * ld + row] -= acc[q];
+                    for (int q = 0; q < 4; ++q) old[u][q] = rv[u] ? gld(W, 8u * (uint32_t)((col + 4 * q) * ld + row)) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NB4; ++u) {
+                    if (!okt[u]) continue;
+                    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+                    const int ra = 16 * jbs[u] + (lane & 15);          // A operand: rows of block jb
+                    const int rb = 16 * ibs[u] + (lane & 15);          // B operand: rows of block ib
+                    const int kq = lane >> 4;
+#pragma unroll
+                    for (int kc = 0; kc < FB; kc += 4) {
+                        double av, bv;
+                        if (in_lds) {
+                            av = panel[(kc + kq) * PR + ra];
+                            bv = panel[(kc + kq) * PR + rb];
+                        } else {
+                            av = gld(W, 8u * (uint32_t)((kb + kc + kq) * ld + r0 + ra));
+                            bv = gld(W, 8u * (uint32_t)((kb + kc + kq) * ld + min(r0 + rb, ld - 1)));
+                        }
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                    }
+                    // FP64 16x16x4 output D[i][j] (lane j + 16 (i % 4), register i / 4):
+                    // acc[q] = sum_k X[16 jb + kq + 4 q][k] X[16 ib + (lane & 15)][k], the update of
+                    // W at row r0 + 16 ib + (lane & 15), column r0 + 16 jb + kq + 4 q
+                    if (rv[u]) {
+                        const int row = r0 + rb;
+                        const int col = r0 + 16 * jbs[u] + kq;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) gst(W, 8u * (uint32_t)((col + 4 * q) * ld + row), old[u][q] - acc[q]);
+                    }
                 }
             }
             __syncthreads();
@@ -341,91 +418,80 @@ __global__ __launch_bounds__(CT) void chol_factor_kernel(const ModDesc* __restri
         }
         __syncthreads();
     }
-    if (s_failed_final) return;
-    // mirror: W[i * ld + j] = L[i][j] for j < i (the upper triangle of the Kp x Kp block)
-    const int total = Kp * Kp;
-    for (int f = tid; f < total; f += CT) {
-        const int i = f / Kp, j = f - i * Kp;
-        if (j < i) W[(int64_t)i * ld + j] = W[(int64_t)j * ld + i];
-    }
 }
 
 // ------------------------------------------------------------------------------------------
-// Solve D A = B row by row: z L^T = b, then d L = z (grid: (ceil(m / 4), dictionaries))
+// Backward substitution D L = Z (one block per dictionary)
 // ------------------------------------------------------------------------------------------
-// One wave per row of D (4 rows per block share the LDS copies of L's diagonal chunks).  Chunks
-// of 64 columns: the contributions of the solved chunks are dot products over coalesced loads of
-// L (lower part for the forward pass, the mirrored upper part for the backward pass); inside the
-// chunk, 64 sequential steps with the chunk's diagonal block in LDS.  The solution overwrites the
-// B rows of W (W[j * ld + Kp + r] = D[r][j]).
-constexpr int SC = 64;
+// Z = B L^{-T} sits in the B rows of W (W[j*ld + Kp + r] = Z[r][j]) and is overwritten by D.
+// Block columns of SB = 32 from the last: T = Z_J - D_{>J} L_{>J,J} on the FP64 matrix cores (the
+// mirrored rows of L give coalesced operands), then D_J L_JJ = T with one thread per row of D
+// (right-looking inside the 32 x 32 block, reciprocals of the diagonal).
+constexpr int TCS = 512;
+constexpr int SB = 32;                       // block columns of the backward substitution
 
-__global__ __launch_bounds__(256) void tri_solve_kernel(const ModDesc* __restrict__ md, int m,
+__global__ __launch_bounds__(TCS) void tri_solve_kernel(const ModDesc* __restrict__ md, int m,
                                                         const int32_t* __restrict__ status) {
-    const int t = blockIdx.y;
+    const int t = blockIdx.x;
     if (status[8 * t + 4]) return;
     const ModDesc d = md[t];
     const int Kp = d.Kpad;
     const int ld = Kp + m;
-    const double* P = d.A;
     double* W = d.W;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r = blockIdx.x * 4 + wave;
-    const bool row_ok = r < m;
-    __shared__ double Lb[SC][SC + 1];
-    __shared__ double zs[4][SMDL_MAX_K];
-    // forward: z_j = (b_j - sum_{i<j} L[j][i] z_i) / L[j][j]
-    for (int J = 0; J < Kp; J += SC) {
-        for (int f = threadIdx.x; f < SC * SC; f += 256) {
-            const int c = f / SC, i = f % SC;                 // Lb[i][c] = L[J+i][J+c]
-            Lb[i][c] = i >= c ? W[(int64_t)(J + c) * ld + J + i] : 0.0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ double Lj[SB][SB + 1];         // Lj[r][c] = L[J + r][J + c]
+    __shared__ double rd[SB];
+    __shared__ double Tt[SMDL_MAX_M][SB + 1]; // right-hand sides of the block column
+    const int MT = (m + 15) / 16;
+    for (int J = Kp - SB; J >= 0; J -= SB) {
+        for (int f = tid; f < SB * SB; f += TCS) {
+            const int c = f / SB, r = f % SB;                         // coalesced down column J + c
+            Lj[r][c] = r >= c ? gld(W, 8u * (uint32_t)((J + c) * ld + J + r)) : 0.0;
         }
-        const int j = J + lane;
-        double tj = row_ok ? P[(int64_t)j * ld + Kp + r] : 0.0;
-        double s0 = 0.0, s1 = 0.0;
-        int i = 0;
-        for (; i + 2 <= J; i += 2) {
-            s0 += W[(int64_t)i * ld + j] * zs[wave][i];
-            s1 += W[(int64_t)(i + 1) * ld + j] * zs[wave][i + 1];
+        if (tid < SB) rd[tid] = 1.0 / gld(W, 8u * (uint32_t)((J + tid) * ld + J + tid));
+        const int kdim = Kp - J - SB;
+        const int kq = lane >> 4;
+        for (int tt = wave; tt < 2 * MT; tt += TCS / 64) {
+            const int rb = tt >> 1, cb = tt & 1;
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+            const int r = min(16 * rb + (lane & 15), m - 1);             // row of D (clamped)
+            for (int k0 = 0; k0 < kdim; k0 += 64) {                   // kdim % 32 == 0
+                double av[16], bv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int i = min(J + SB + k0 + 4 * u + kq, Kp - 1);
+                    av[u] = gld(W, 8u * (uint32_t)(i * ld + Kp + r));                        // D[r][i]
+                    bv[u] = gld(W, 8u * (uint32_t)(i * ld + J + 16 * cb + (lane & 15)));      // L[i][J + c]
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (k0 + 4 * u < kdim) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+            }
+            // acc[q]: row 16 rb + kq + 4 q of D, column 16 cb + (lane & 15) of the block
+            const int c = 16 * cb + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * rb + kq + 4 * q;
+                if (row < m) Tt[row][c] = gld(W, 8u * (uint32_t)((J + c) * ld + Kp + row)) - acc[q];
+            }
         }
-        for (; i < J; ++i) s0 += W[(int64_t)i * ld + j] * zs[wave][i];
-        tj -= s0 + s1;
         __syncthreads();
-        for (int jj = 0; jj < SC; ++jj) {
-            const double zj = readlane_f64(tj / Lb[lane][lane], jj);
-            if (lane > jj) tj = fma(-Lb[lane][jj], zj, tj);
-            if (lane == jj) tj = zj;
+        if (tid < m) {
+            double x[SB];
+#pragma unroll
+            for (int c = 0; c < SB; ++c) x[c] = Tt[tid][c];
+#pragma unroll
+            for (int c = SB - 1; c >= 0; --c) {
+                x[c] *= rd[c];
+#pragma unroll
+                for (int c2 = 0; c2 < c; ++c2) x[c2] = fma(-x[c], Lj[c][c2], x[c2]);
+                __asm__ volatile("" ::: "memory");         // keep row c's LDS reads in this step
+            }
+#pragma unroll
+            for (int c = 0; c < SB; ++c) gst(W, 8u * (uint32_t)((J + c) * ld + Kp + tid), x[c]);
         }
-        zs[wave][j] = tj;
         __syncthreads();
     }
-    // backward: d_j = (z_j - sum_{i>j} L[i][j] d_i) / L[j][j], L[i][j] = W[i * ld + j] (mirror)
-    for (int J = Kp - SC; J >= 0; J -= SC) {
-        for (int f = threadIdx.x; f < SC * SC; f += 256) {
-            const int c = f / SC, i = f % SC;
-            Lb[i][c] = i >= c ? W[(int64_t)(J + c) * ld + J + i] : 0.0;
-        }
-        const int j = J + lane;
-        double tj = zs[wave][j];
-        double s0 = 0.0, s1 = 0.0;
-        int i = J + SC;
-        for (; i + 2 <= Kp; i += 2) {
-            s0 += W[(int64_t)i * ld + j] * zs[wave][i];
-            s1 += W[(int64_t)(i + 1) * ld + j] * zs[wave][i + 1];
-        }
-        for (; i < Kp; ++i) s0 += W[(int64_t)i * ld + j] * zs[wave][i];
-        tj -= s0 + s1;
-        __syncthreads();
-        for (int jj = SC - 1; jj >= 0; --jj) {
-            const double dj = readlane_f64(tj / Lb[lane][lane], jj);
-            if (lane < jj) tj = fma(-Lb[jj][lane], dj, tj);
-            if (lane == jj) tj = dj;
-        }
-        zs[wave][j] = tj;                                    // z of this chunk is now d
-        __syncthreads();
-    }
-    if (row_ok)
-        for (int j = lane; j < Kp; j += 64) W[(int64_t)j * ld + Kp + r] = zs[wave][j];
 }
 
 // Unit-normalise the solved atoms and store them (one wave per atom).
@@ -477,7 +543,7 @@ hipError_t launch_mod(const ModDesc* dev_desc, const ModDesc* host_desc, int n_d
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(tri_solve_kernel, dim3((m + 3) / 4, n_desc), dim3(256), 0, st, dev_desc, m, status);
+    hipLaunchKernelGGL(tri_solve_kernel, dim3(n_desc), dim3(TCS), 0, st, dev_desc, m, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(mod_normalize_kernel, dim3((max_kpad + 3) / 4, n_desc), dim3(256), 0, st, dev_desc, m, status);
     return hipGetLastError();
