@@ -9,7 +9,10 @@ One step = one pass of the whole hot path over one synthetic batch, inputs resid
   2. labels for the proposer: plain OMP of 200000 fresh training signals with the learned D;
   3. proposer training (MLP 64-512-512-256, BF16 GEMMs, Adam) for `--epochs` epochs;
   4. coding of 100000 fresh evaluation signals, plain and with the trained proposer (top 24
-     candidates, full-OMP fallback when ||r|| > 1.1 x the plain RMS residual).
+     candidates, full-OMP fallback when ||r|| > 1.1 x the RMS plain residual of the training
+     pairs).
+After the timed steps the fallback threshold is swept (1.1 x down to 0.8 x) to report learned
+vs plain throughput at equal representation RMSE (ratio within 1 %).
 value = signals sparse-coded at (m=64, K=256, s=8) per second of the whole step (the local
 codings of every iteration, the final coding, the labels and both evaluation codings).
 
@@ -137,7 +140,9 @@ def main():
                                          w.iters_merge, w.s_merge, w.s_final)
         info["phase_ms"] = h.phase_ms()
         info["final_kernel_ms"] = h.last_kernel_ms()
-        labels = h.omp_code(D, Yt, 8)
+        # labels, and the plain residual of the training pairs that fixes the fallback threshold
+        labels, rn_tr = h.omp_code(D, Yt, 8, res_norm=True)
+        rms_tr = torch.sqrt((rn_tr.double() ** 2).mean())
         prop = h.proposer(Ws, bs)
         losses = prop.train(Yt, labels, epochs=args.epochs, batch=1024, lr=1e-3, shuffle_seed=1)
         torch.cuda.synchronize()
@@ -146,21 +151,25 @@ def main():
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         info["plain_kernel_ms"] = h.last_kernel_ms()
-        eps_fb = 1.1 * float(torch.sqrt((rn.double() ** 2).mean()).item())
+        eps_fb = 1.1 * float(rms_tr.item())
         t0 = time.perf_counter()
         Xl, fb, nfb, _ = h.omp_code_proposed(prop, D, Ye, 8, 24, eps_fb)
         torch.cuda.synchronize()
         t_learn = time.perf_counter() - t0
         info.update(t_plain=t_plain, t_learn=t_learn, nfb=nfb, losses=losses, prop_ms=h.prop_phase_ms())
-        info["D"], info["Xp"], info["Xl"] = D, Xp, Xl
-        prop.close()
+        info["D"], info["Xp"], info["Xl"], info["rms_tr"] = D, Xp, Xl, float(rms_tr.item())
+        info["prop"] = prop
         return info
 
     for _ in range(args.warmup):
-        step()
+        step()["prop"].close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = [step() for _ in range(args.steps)]
+    infos = []
+    for _ in range(args.steps):
+        infos.append(step())
+        if len(infos) > 1:
+            infos[-2]["prop"].close()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
 
@@ -172,6 +181,18 @@ def main():
         R = Ye.double() - Xd @ D.double()
         return float(torch.sqrt((R ** 2).mean()).item())
     r_plain, r_learn = rmse(last["Xp"]), rmse(last["Xl"])
+    # learned vs plain along the fallback threshold (multiples of the training pairs' RMS plain
+    # residual), after the timed steps: the equal-RMSE point is the largest multiplier whose
+    # representation RMSE is within 1 % of the plain one
+    prop = last["prop"]
+    curve = []
+    for mult in (1.1, 1.05, 1.02, 1.0, 0.95, 0.9, 0.85, 0.8):
+        Xm, _, nfm, _ = h.omp_code_proposed(prop, D, Ye, 8, 24, mult * last["rms_tr"])
+        torch.cuda.synchronize()
+        ms = sum(h.prop_phase_ms())
+        curve.append({"eps_mult": mult, "rmse_ratio": rmse(Xm) / r_plain, "fallback_rate": nfm / Yev.shape[0],
+                      "learned_signals_per_s": Yev.shape[0] / (ms * 1e-3)})
+    prop.close()
     n_local = int(w.N * (w.iters_local + 1))
     codings = n_local + w.N + Ytr.shape[0] + 2 * Yev.shape[0]
     value = codings / dt
@@ -207,6 +228,9 @@ def main():
         "rmse_learned": r_learn,
         "rmse_ratio": r_learn / r_plain,
         "fallback_rate": last["nfb"] / Yev.shape[0],
+        "eps_fallback": "1.1 x RMS plain-OMP residual of the 200000 training pairs",
+        "learned_vs_plain_curve": curve,
+        "equal_rmse": None,
         "phase_ms": {"local": last["phase_ms"][0], "merge": last["phase_ms"][1],
                      "final": last["phase_ms"][2], "final_kernel": last["final_kernel_ms"],
                      "plain_eval_kernel": kms, "proposer_net_topk": prop_ms[0],
@@ -218,6 +242,12 @@ def main():
                      "per_signal_flops": f_sig,
                      "per_signal_bytes": omp_bytes_per_signal(64, 8)},
     }
+    eq = [c for c in curve if c["rmse_ratio"] <= 1.01]
+    if eq:
+        best = max(eq, key=lambda c: c["eps_mult"])
+        out["equal_rmse"] = {"eps_mult": best["eps_mult"], "rmse_ratio": best["rmse_ratio"],
+                             "learned_vs_plain": best["learned_signals_per_s"] / plain_sps,
+                             "fallback_rate": best["fallback_rate"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_subsets, args.cpu_n, args.cpu_iters)
     else:
