@@ -4,7 +4,11 @@
 // with both operands stored with the reduction dimension contiguous, on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Fragments are loaded straight from global
 // memory (16 bytes per lane); the four waves of a block split the reduction of one 32 x 32
-// output tile, each issuing the loads of four k-steps at once, and sum their partials in LDS.  The layouts that make every product NT:
+// output tile, each issuing the loads of four k-steps at once, and sum their partials in LDS.
+// The BF16 weights and the transposed activations and deltas are stored in fragment order (see
+// pk_off), so that the 64 lanes of a fragment load read one contiguous kilobyte; in row-major
+// order the 16 lanes of a k-group would touch 16 different rows, and the vector L1 cache would
+// serve the load one lane at a time.  The layouts that make every product NT:
 //   forward   h_l   [B x w_l]   = h_{l-1} [B x w_{l-1}] . W_l [w_l x w_{l-1}]^T
 //   backward  d_{l-1} [B x w_{l-1}] = d_l [B x w_l] . W_l^T [w_{l-1} x w_l]^T   (ReLU mask)
 //   weights   dW_l [w_l x w_{l-1}] = d_l^T [w_l x B] . h_{l-1}^T [w_{l-1} x B]^T
@@ -27,21 +31,42 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint
 constexpr int TILE = 32;       // output tile of a block (rows and columns)
 constexpr int RP = TILE + 1;   // LDS row of an FP32 tile
 
+// Fragment order of an [N x K] BF16 matrix (N % 16 == 0, K % 32 == 0): one kilobyte per block
+// of 16 rows and 32 columns, blocks ordered by row block then column block; inside a block, lane
+// l = (n % 16) + 16 ((k % 32) / 8) of a v_mfma_f32_16x16x32_bf16 operand holds the 8 consecutive
+// entries k = 8 ((k % 32) / 8) .. + 7 of row n.  The offset of entry (n, k), in elements:
+__device__ __forceinline__ int64_t pk_off(int n, int k, int K) {
+    return ((((int64_t)(n >> 4) * (K >> 5) + (k >> 5)) * 64 + ((n & 15) + 16 * ((k & 31) >> 3))) << 3) + (k & 7);
+}
+// Lane's fragment of row block nb, k-step 0, of a fragment-ordered matrix; k-step st is 512
+// elements further.
+__device__ __forceinline__ const uint16_t* pk_frag(const uint16_t* base, int nb, int K, int lane) {
+    return base + (((int64_t)nb * (K >> 5)) * 64 + lane) * 8;
+}
+
 // Partial 32 x 32 tile (m0, n0) of A B^T over the k-steps (32 wide) wave, wave + 4, ...:
 // 2 x 2 blocks of 16 x 16; the loads of up to four k-steps are issued before their MFMAs.
-// Rows >= M of A and columns >= N of B are read clamped (their results are discarded).
+// A is row-major (ld lda; rows >= M read clamped, their results discarded) or, with A_PK, in
+// fragment order; B is in fragment order (N % 32 == 0).
+template <bool A_PK>
 __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int lda, int M,
-                                           const uint16_t* __restrict__ B, int ldb, int N, int K,
+                                           const uint16_t* __restrict__ B, int K,
                                            int m0, int n0, int wave, int lane, f32x4 (&acc)[2][2]) {
     const int r16 = lane & 15, kq = lane >> 4;
     const uint16_t* ap[2];
     const uint16_t* bp[2];
+    int astep;
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-        const int r = min(m0 + 16 * f + r16, M - 1);
-        const int c = min(n0 + 16 * f + r16, N - 1);
-        ap[f] = A + (int64_t)r * lda + 8 * kq;
-        bp[f] = B + (int64_t)c * ldb + 8 * kq;
+        if (A_PK) {
+            ap[f] = pk_frag(A, (m0 >> 4) + f, K, lane);
+            astep = 512;
+        } else {
+            const int r = min(m0 + 16 * f + r16, M - 1);
+            ap[f] = A + (int64_t)r * lda + 8 * kq;
+            astep = 32;
+        }
+        bp[f] = pk_frag(B, (n0 >> 4) + f, K, lane);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -55,8 +80,8 @@ __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int l
             const int st = min(s0 + 4 * c, nsteps - 1);
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
-                a[c][f] = *reinterpret_cast<const bf16x8*>(ap[f] + 32 * st);
-                b[c][f] = *reinterpret_cast<const bf16x8*>(bp[f] + 32 * st);
+                a[c][f] = *reinterpret_cast<const bf16x8*>(ap[f] + (int64_t)astep * st);
+                b[c][f] = *reinterpret_cast<const bf16x8*>(bp[f] + (int64_t)512 * st);
             }
         }
 #pragma unroll
@@ -72,12 +97,13 @@ __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int l
 }
 
 // The full 32 x 32 tile: the four waves' partials summed through LDS into tile[r][c].
+template <bool A_PK>
 __device__ __forceinline__ void nt_tile(const uint16_t* __restrict__ A, int lda, int M,
-                                        const uint16_t* __restrict__ B, int ldb, int N, int K,
+                                        const uint16_t* __restrict__ B, int K,
                                         int m0, int n0, float (*part)[TILE][RP], float (*tile)[RP]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     f32x4 acc[2][2];
-    nt_partial(A, lda, M, B, ldb, N, K, m0, n0, wave, lane, acc);
+    nt_partial<A_PK>(A, lda, M, B, K, m0, n0, wave, lane, acc);
     // D[i][j] of a 16 x 16 block sits in lane j + 16 (i / 4), register i % 4
     const int r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -117,7 +143,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
         const int src = g.rows ? g.rows[row] : row;
         tbits = g.tmask[(int64_t)src * g.tstride + ((n0 + cl0) >> 5)] >> ((n0 + cl0) & 31);
     }
-    nt_tile(g.A, g.lda, g.M, g.B, g.ldb, g.N, g.K, m0, n0, part, tile);
+    nt_tile<false>(g.A, g.lda, g.M, g.B, g.K, m0, n0, part, tile);
 
     double lsum = 0.0;
     float v[4];
@@ -180,12 +206,13 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
     }
     if (g.tmask && tid == 0) atomicAdd(g.loss, (lred[0] + lred[1]) + (lred[2] + lred[3]));
     if (g.outT) {
-        // thread t: column t / 8 of the tile, rows 4 (t % 8) .. + 3 -> 8 bytes of a row of out^T
+        // thread t: column t / 8 of the tile, rows 4 (t % 8) .. + 3 -> 8 bytes of out^T
+        // ([N x M] in fragment order)
         const int c = tid >> 3, r0 = (tid & 7) * 4;
         if (n0 + c < g.N) {
             const uint32_t lo = (uint32_t)tT[c][r0] | ((uint32_t)tT[c][r0 + 1] << 16);
             const uint32_t hi = (uint32_t)tT[c][r0 + 2] | ((uint32_t)tT[c][r0 + 3] << 16);
-            *reinterpret_cast<uint2*>(g.outT + (int64_t)(n0 + c) * g.ldt + m0 + r0) = make_uint2(lo, hi);
+            *reinterpret_cast<uint2*>(g.outT + pk_off(n0 + c, m0 + r0, g.M)) = make_uint2(lo, hi);
         }
     }
 }
@@ -240,7 +267,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs g) {
     const WgLayer& L = g.L[l];
     const int t = blk - L.tile0;
     const int m0 = (t / L.ntn) * TILE, n0 = (t % L.ntn) * TILE;    // rows o, columns i
-    nt_tile(L.dT, g.Bpad, L.wo, L.hT, g.Bpad, L.wi, g.Bpad, m0, n0, part, tile);
+    nt_tile<true>(L.dT, 0, L.wo, L.hT, g.Bpad, m0, n0, part, tile);
     const int ol = tid >> 3, il0 = (tid & 7) * 4;
     const int o = m0 + ol, i0 = n0 + il0;
     const bool ok = o < L.wo && i0 < L.wi;       // wi % 4 == 0
@@ -269,16 +296,16 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs g) {
         *reinterpret_cast<float4*>(L.mW + idx) = make_float4(mm[0], mm[1], mm[2], mm[3]);
         *reinterpret_cast<float4*>(L.vW + idx) = make_float4(vv[0], vv[1], vv[2], vv[3]);
         *reinterpret_cast<float4*>(L.W + idx) = make_float4(ww[0], ww[1], ww[2], ww[3]);
-        *reinterpret_cast<uint2*>(L.Wbf + idx) =
+        *reinterpret_cast<uint2*>(L.Wpk + pk_off(o, i0, L.wi)) =
             make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
     }
     __syncthreads();
-    // W^T: thread t writes column i = t / 8, rows o = 4 (t % 8) .. + 3 (wo % 4 == 0)
+    // W^T: thread t writes row i = t / 8, entries o = 4 (t % 8) .. + 3
     const int ic = tid >> 3, o0 = (tid & 7) * 4;
     if (n0 + ic < L.wi && m0 + o0 < L.wo) {
         const uint32_t lo = (uint32_t)tT[ic][o0] | ((uint32_t)tT[ic][o0 + 1] << 16);
         const uint32_t hi = (uint32_t)tT[ic][o0 + 2] | ((uint32_t)tT[ic][o0 + 3] << 16);
-        *reinterpret_cast<uint2*>(L.WbfT + (int64_t)(n0 + ic) * L.wo + m0 + o0) = make_uint2(lo, hi);
+        *reinterpret_cast<uint2*>(L.WTpk + pk_off(n0 + ic, m0 + o0, L.wo)) = make_uint2(lo, hi);
     }
 }
 
@@ -332,10 +359,304 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ Y, 
     }
     if (!h0T) return;
     __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int i = wave; i < m; i += 4)
-        if ((int64_t)blockIdx.x * PREP_ROWS + lane < Bpad)
-            h0T[(int64_t)i * Bpad + (int64_t)blockIdx.x * PREP_ROWS + lane] = t[lane][i];
+    // h0^T ([m x Bpad] in fragment order): thread t writes rows 4 (t % 16) .. + 3 of column t / 16
+    for (int q = tid; q < m * (PREP_ROWS / 4); q += 256) {
+        const int i = q / (PREP_ROWS / 4), rc = (q % (PREP_ROWS / 4)) * 4;
+        const uint32_t lo = (uint32_t)t[rc][i] | ((uint32_t)t[rc + 1][i] << 16);
+        const uint32_t hi = (uint32_t)t[rc + 2][i] | ((uint32_t)t[rc + 3][i] << 16);
+        *reinterpret_cast<uint2*>(h0T + pk_off(i, (int)((int64_t)blockIdx.x * PREP_ROWS + rc), (int)Bpad)) =
+            make_uint2(lo, hi);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The whole network on R batch rows per work group (see RowsArgs).  512 threads = 8 waves.  The
+// output of a layer is cut into 32-column tiles that the waves take in turn; a tile is R x 32 =
+// (R / 16) x 2 blocks of 16 x 16 on v_mfma_f32_16x16x32_bf16.  A fragments come from the BF16
+// activations in LDS, B fragments (weight rows, L2 resident) from global memory, the loads of
+// the next four k-steps issued before the current four are multiplied.  Every activation of the
+// R rows stays in LDS until the backward pass has used it as a ReLU mask; each delta overwrites
+// the activation that masked it.
+constexpr int FT = 512;        // threads of the fused network kernel
+constexpr int ACT_PAD = 8;     // BF16 padding per LDS activation row (16 bytes: rows 4 banks apart)
+
+// B fragments (fragment-ordered weight row blocks n0 / 16 and n0 / 16 + 1) of k-steps s .. s + 3
+// (clamped; a step past the end is loaded but not used).
+__device__ __forceinline__ void rows_load_b(bf16x8 (&b)[4][2], const uint16_t* bp0, const uint16_t* bp1, int s,
+                                            int nsteps) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int st = min(s + c, nsteps - 1);
+        b[c][0] = *reinterpret_cast<const bf16x8*>(bp0 + 512 * st);
+        b[c][1] = *reinterpret_cast<const bf16x8*>(bp1 + 512 * st);
+    }
+}
+
+// k-steps s .. s + 3 of a tile: the A fragments of the four steps are read from LDS first.
+template <int RB>
+__device__ __forceinline__ void rows_mma4(f32x4 (&acc)[RB][2], const bf16x8 (&b)[4][2], const uint16_t* ap, int lda,
+                                          int s, int nsteps) {
+    bf16x8 a[4][RB];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int st = min(s + c, nsteps - 1);
+#pragma unroll
+        for (int i = 0; i < RB; ++i) a[c][i] = *reinterpret_cast<const bf16x8*>(ap + i * 16 * lda + 32 * st);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (s + c < nsteps) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c][i], b[c][0], acc[i][0], 0, 0, 0);
+                acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c][i], b[c][1], acc[i][1], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// acc = rows 0 .. R - 1 of A (LDS, ld lda) times weight rows n0 .. n0 + 31 of Bw (fragment order)
+// over K.  The B fragments go through two register sets in turn: the loads of the next four
+// k-steps are in flight while the current four are multiplied.  Every iteration issues both
+// sets' loads unconditionally (clamped to the last step), so that no set is overwritten or read
+// while loads of another path may still be pending into it.
+template <int RB>
+__device__ __forceinline__ void rows_tile(const uint16_t* __restrict__ A, int lda, const uint16_t* __restrict__ Bw,
+                                          int K, int n0, int lane, f32x4 (&acc)[RB][2]) {
+    const int r16 = lane & 15, kq = lane >> 4;
+    const uint16_t* bp0 = pk_frag(Bw, n0 >> 4, K, lane);
+    const uint16_t* bp1 = pk_frag(Bw, (n0 >> 4) + 1, K, lane);
+    const uint16_t* ap = A + r16 * lda + 8 * kq;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        acc[i][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int nsteps = K >> 5;
+    bf16x8 b0[4][2], b1[4][2];
+    rows_load_b(b0, bp0, bp1, 0, nsteps);
+    for (int s0 = 0; s0 < nsteps; s0 += 8) {
+        rows_load_b(b1, bp0, bp1, s0 + 4, nsteps);
+        rows_mma4<RB>(acc, b0, ap, lda, s0, nsteps);
+        rows_load_b(b0, bp0, bp1, s0 + 8, nsteps);
+        rows_mma4<RB>(acc, b1, ap, lda, s0 + 4, nsteps);
+    }
+}
+
+// Stores the FP32 deltas v of a tile (row 16 i + 4 kq + q, column n0 + 16 j + r16 of the lane):
+// BF16 into LDS (when O is set), BF16 transposed into dT ([w x Bpad] in fragment order) and the column sums over
+// the R rows into colpart[block][w].
+template <int RB>
+__device__ __forceinline__ void store_deltas(const float (&v)[RB][2][4], uint16_t* O, int ldo, uint16_t* dT,
+                                             int64_t Bpad, int64_t r0, float* colpart, int w, int n0, int lane) {
+    const int r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = n0 + 16 * j + r16;
+        float cs = 0.f;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            uint16_t hb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                hb[q] = f2bf(v[i][j][q]);
+                cs += v[i][j][q];
+                if (O) O[(16 * i + 4 * kq + q) * ldo + col] = hb[q];
+            }
+            *reinterpret_cast<uint2*>(dT + pk_off(col, (int)(r0 + 16 * i + 4 * kq), (int)Bpad)) =
+                make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16), (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+        }
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        if (kq == 0) colpart[(int64_t)blockIdx.x * w + col] = cs;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(FT) void mlp_rows_kernel(RowsArgs g) {
+    constexpr int RB = R / 16;
+    extern __shared__ __align__(16) uint16_t act[];
+    __shared__ int32_t s_src[R];
+    __shared__ double s_loss[FT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int L = g.n_layers;
+    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const bool train = g.tmask != nullptr;
+    // LDS rows of the input of layer l (l = L: the output deltas)
+    auto buf = [&](int l) -> uint16_t* {
+        int off = 0;
+        for (int i = 0; i < l; ++i) off += R * (g.w[i] + ACT_PAD);
+        return act + off;
+    };
+    // ---- input rows: h0 = bf16(y / ||y||), zero for rows >= B
+    const int m = g.w[0];
+    if (tid < R) {
+        const int64_t gr = r0 + tid;
+        s_src[tid] = gr < g.B ? (g.rows ? g.rows[gr] : (int32_t)gr) : -1;
+    }
+    __syncthreads();
+    {
+        constexpr int TPR = FT / R;                  // threads per row (16 or 32), lanes of one wave
+        constexpr int NCH = SMDL_MAX_M / 4 / TPR;    // float4 chunks per thread at most
+        const int rr = tid / TPR, pt = tid % TPR;
+        const int src = s_src[rr];
+        const bool vec = (reinterpret_cast<uintptr_t>(g.Y) & 15) == 0;
+        float4 yv[NCH];
+        float ss = 0.f;
+#pragma unroll
+        for (int it = 0; it < NCH; ++it) {
+            const int c = pt + TPR * it;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (src >= 0 && 4 * c < m) {
+                const float* yp = g.Y + (int64_t)src * m + 4 * c;
+                v = vec ? *reinterpret_cast<const float4*>(yp) : make_float4(yp[0], yp[1], yp[2], yp[3]);
+            }
+            yv[it] = v;
+            ss = fmaf(v.x, v.x, fmaf(v.y, v.y, fmaf(v.z, v.z, fmaf(v.w, v.w, ss))));
+        }
+#pragma unroll
+        for (int off = 1; off < TPR; off <<= 1) ss += __shfl_xor(ss, off, 64);
+        const float inv = ss > 0.f ? 1.0f / sqrtf(ss) : 0.f;
+        uint16_t* h0 = act + rr * (m + ACT_PAD);
+#pragma unroll
+        for (int it = 0; it < NCH; ++it) {
+            const int c = pt + TPR * it;
+            if (4 * c < m) {
+                const float4 v = yv[it];
+                const uint32_t lo = (uint32_t)f2bf(v.x * inv) | ((uint32_t)f2bf(v.y * inv) << 16);
+                const uint32_t hi = (uint32_t)f2bf(v.z * inv) | ((uint32_t)f2bf(v.w * inv) << 16);
+                *reinterpret_cast<uint2*>(h0 + 4 * c) = make_uint2(lo, hi);
+            }
+        }
+    }
+    __syncthreads();
+    if (train) {
+        // h0^T: thread t writes rows 4 (t % (R / 4)) .. + 3 of column t / (R / 4)
+        const int ld0 = m + ACT_PAD;
+        for (int t = tid; t < m * (R / 4); t += FT) {
+            const int i = t / (R / 4), rc = (t % (R / 4)) * 4;
+            const uint16_t* c0 = act + rc * ld0 + i;
+            const uint32_t lo = (uint32_t)c0[0] | ((uint32_t)c0[ld0] << 16);
+            const uint32_t hi = (uint32_t)c0[2 * ld0] | ((uint32_t)c0[3 * ld0] << 16);
+            *reinterpret_cast<uint2*>(g.hT[0] + pk_off(i, (int)(r0 + rc), (int)g.Bpad)) = make_uint2(lo, hi);
+        }
+    }
+    // ---- forward
+    double lsum = 0.0;
+    for (int l = 0; l < L; ++l) {
+        const int wi = g.w[l], wo = g.w[l + 1];
+        const bool last = l + 1 == L;
+        const uint16_t* A = buf(l);
+        uint16_t* O = buf(l + 1);
+        const int lda = wi + ACT_PAD, ldo = wo + ACT_PAD;
+        for (int ct = wave; ct < wo / 32; ct += FT / 64) {
+            const int n0 = 32 * ct;
+            const float bj[2] = {g.bias[l][n0 + r16], g.bias[l][n0 + 16 + r16]};
+            f32x4 acc[RB][2];
+            rows_tile<RB>(A, lda, g.W[l], wi, n0, lane, acc);
+            if (!last) {
+                // ReLU; BF16 into LDS (next layer's input) and transposed into hT[l + 1]
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int col = n0 + 16 * j + r16;
+#pragma unroll
+                    for (int i = 0; i < RB; ++i) {
+                        uint16_t hb[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int row = 16 * i + 4 * kq + q;
+                            const float x = s_src[row] >= 0 ? fmaxf(acc[i][j][q] + bj[j], 0.f) : 0.f;
+                            hb[q] = f2bf(x);
+                            O[row * ldo + col] = hb[q];
+                        }
+                        if (train)
+                            *reinterpret_cast<uint2*>(g.hT[l + 1] + pk_off(col, (int)(r0 + 16 * i + 4 * kq), (int)g.Bpad)) =
+                                make_uint2((uint32_t)hb[0] | ((uint32_t)hb[1] << 16),
+                                           (uint32_t)hb[2] | ((uint32_t)hb[3] << 16));
+                    }
+                }
+            } else if (!train) {
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = 16 * i + 4 * kq + q;
+                        if (s_src[row] < 0) continue;
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            g.logits[(r0 + row) * wo + n0 + 16 * j + r16] = acc[i][j][q] + bj[j];
+                    }
+            } else {
+                // BCE with logits: loss max(z,0) - t z + log(1 + e^-|z|), delta (sigmoid(z) - t) s
+                float v[RB][2][4];
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int src = s_src[16 * i + 4 * kq + q];
+                        const uint32_t word = src >= 0 ? g.tmask[(int64_t)src * g.tstride + ct] : 0u;
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            float x = 0.f;
+                            if (src >= 0) {
+                                const float z = acc[i][j][q] + bj[j];
+                                const float t = (float)((word >> (16 * j + r16)) & 1u);
+                                const float sg = 1.0f / (1.0f + expf(-z));
+                                lsum += (double)(fmaxf(z, 0.f) - t * z + log1pf(expf(-fabsf(z))));
+                                x = (sg - t) * g.scale;
+                            }
+                            v[i][j][q] = x;
+                        }
+                    }
+                store_deltas<RB>(v, L > 1 ? O : nullptr, ldo, g.dT[l], g.Bpad, r0, g.colpart[l], wo, n0, lane);
+            }
+        }
+        __syncthreads();
+    }
+    if (!train) return;
+    // ---- backward: d[l-1] = (d[l] W_l) * [h_l > 0], written over h_l
+    for (int l = L - 1; l >= 1; --l) {
+        const int wi = g.w[l], wo = g.w[l + 1];
+        const uint16_t* A = buf(l + 1);
+        uint16_t* H = buf(l);
+        const int lda = wo + ACT_PAD, ldh = wi + ACT_PAD;
+        for (int ct = wave; ct < wi / 32; ct += FT / 64) {
+            const int n0 = 32 * ct;
+            f32x4 acc[RB][2];
+            rows_tile<RB>(A, lda, g.WT[l], wo, n0, lane, acc);
+            float v[RB][2][4];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = 16 * i + 4 * kq + q;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const float hm = bf2f(H[row * ldh + n0 + 16 * j + r16]);
+                        v[i][j][q] = (hm > 0.f && s_src[row] >= 0) ? acc[i][j][q] : 0.f;
+                    }
+                }
+            store_deltas<RB>(v, l - 1 >= 1 ? H : nullptr, ldh, g.dT[l - 1], g.Bpad, r0, g.colpart[l - 1], wi, n0, lane);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) s_loss[wave] = lsum;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < FT / 64; ++w) s += s_loss[w];
+        atomicAdd(g.loss, s);
+    }
+}
+
+size_t rows_lds_bytes(int n_layers, const int* w, int R) {
+    size_t b = 0;
+    for (int l = 0; l <= n_layers; ++l) b += (size_t)R * 2 * (w[l] + ACT_PAD);
+    return b;
 }
 
 // Multi-hot bitmask of the ELL labels: mask[n][w] bit k%32 of word k/32 set for every label k.
@@ -353,14 +674,14 @@ __global__ void label_mask_kernel(const int32_t* __restrict__ idx, const int32_t
     }
 }
 
-// BF16 copies W and W^T of FP32 masters.
+// BF16 copies of an FP32 master W [rows x cols] in fragment order: W itself and W^T.
 __global__ void to_bf16_kernel(const float* __restrict__ w, int64_t n, int cols, int rows,
-                               uint16_t* __restrict__ wbf, uint16_t* __restrict__ wbfT) {
+                               uint16_t* __restrict__ wpk, uint16_t* __restrict__ wtpk) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const uint16_t h = f2bf(w[i]);
-        wbf[i] = h;
         const int r = (int)(i / cols), c = (int)(i % cols);
-        wbfT[(int64_t)c * rows + r] = h;
+        wpk[pk_off(r, c, cols)] = h;
+        wtpk[pk_off(c, r, rows)] = h;
     }
 }
 
@@ -380,8 +701,44 @@ inline int grid_n(int64_t n) {
 
 }  // namespace
 
+int mlp_rows_per_block(int n_layers, const int* widths, bool train) {
+    if (n_layers < 1 || n_layers > 4) return 0;
+    if (widths[0] > SMDL_MAX_M) return 0;
+    for (int l = 0; l <= n_layers; ++l)
+        if (widths[l] < 32 || widths[l] % 32) return 0;
+    const size_t budget = SMDL_LDS_BYTES - 1024;    // the static arrays
+    if (!train && rows_lds_bytes(n_layers, widths, 32) <= budget) return 32;
+    if (rows_lds_bytes(n_layers, widths, 16) <= budget) return 16;
+    return 0;
+}
+
+hipError_t launch_mlp_rows(const RowsArgs& a, int R, hipStream_t st) {
+    if ((R != 16 && R != 32) || a.Bpad < R || a.Bpad % R || a.B > a.Bpad) return hipErrorInvalidValue;
+    const size_t budget = SMDL_LDS_BYTES - 1024;
+    if (mlp_rows_per_block(a.n_layers, a.w, false) == 0 || rows_lds_bytes(a.n_layers, a.w, R) > budget)
+        return hipErrorInvalidValue;
+    if (a.tmask ? (!a.loss || a.tstride < (a.w[a.n_layers] + 31) / 32) : !a.logits) return hipErrorInvalidValue;
+    const size_t lds = rows_lds_bytes(a.n_layers, a.w, R);
+    static bool attr_set = false;   // both instantiations may use the whole LDS budget
+    if (!attr_set) {
+        const int full = (int)(SMDL_LDS_BYTES - 1024);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_rows_kernel<32>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, full);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_rows_kernel<16>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, full);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    if (R == 32)
+        hipLaunchKernelGGL(mlp_rows_kernel<32>, dim3((unsigned)(a.Bpad / 32)), dim3(FT), lds, st, a);
+    else
+        hipLaunchKernelGGL(mlp_rows_kernel<16>, dim3((unsigned)(a.Bpad / 16)), dim3(FT), lds, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm_nt(const NtArgs& g, hipStream_t st) {
-    if (g.M % TILE || g.K % 32 || g.N < 4 || g.N % 4 || g.M < TILE || g.lda % 8 || g.ldb % 8) return hipErrorInvalidValue;
+    if (g.M % TILE || g.K % 32 || g.N < TILE || g.N % TILE || g.M < TILE || g.lda % 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(gemm_nt_kernel, dim3((g.N + TILE - 1) / TILE, g.M / TILE), dim3(256), 0, st, g);
     return hipGetLastError();
 }
@@ -391,7 +748,7 @@ hipError_t launch_wgrad(WgArgs& g, hipStream_t st) {
     int blocks = 0;
     for (int l = 0; l < g.n_layers; ++l) {
         WgLayer& L = g.L[l];
-        if (L.wo % 4 || L.wi % 4) return hipErrorInvalidValue;
+        if (L.wo % TILE || L.wi % TILE) return hipErrorInvalidValue;
         L.tile0 = blocks;
         L.ntn = (L.wi + TILE - 1) / TILE;
         blocks += ((L.wo + TILE - 1) / TILE) * L.ntn;

@@ -15,7 +15,7 @@ struct smdl_prop {
     int n_layers = 0;
     std::vector<int> widths;
     std::vector<float*> W, b, mW, vW, mb, vb;   // FP32 masters and Adam moments
-    std::vector<uint16_t*> Wbf, WbfT;           // BF16 copies (out x in) and (in x out)
+    std::vector<uint16_t*> Wpk, WTpk;           // BF16 W (out x in) and W^T (in x out), fragment order
     int step = 0;                               // Adam steps taken
     int32_t* dstep = nullptr;                   // the same count on the device
     std::vector<void*> allocs;
@@ -36,9 +36,12 @@ namespace {
 
 inline int64_t pad64b(int64_t x) { return (x + 63) / 64 * 64; }
 
-// Activation buffers for a batch of Bpad rows (a multiple of 64).
+// Activation buffers for a batch of Bpad rows (a multiple of 64).  With R > 0 the fused
+// network kernel runs R rows per work group and keeps the row-major activations and deltas in
+// LDS, so only the transposed copies, the column sums and the logits live here.
 struct Acts {
     int64_t Bpad = 0;
+    int R = 0;
     std::vector<uint16_t*> h;      // h[l]: Bpad x widths[l], input of layer l (BF16)
     float* logits = nullptr;       // Bpad x K (inference)
     // training only
@@ -51,8 +54,9 @@ struct Acts {
 smdl_status get_acts(smdl_t h, smdl_prop_t p, int64_t Bpad, bool train, Acts& a) {
     const int L = p->n_layers;
     a.Bpad = Bpad;
+    a.R = mlp_rows_per_block(L, p->widths.data(), train);
     a.h.assign(L, nullptr);
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < L && a.R == 0; ++l) {
         std::string nm = "prop.h" + std::to_string(l);
         a.h[l] = (uint16_t*)h->ws(nm.c_str(), (size_t)Bpad * p->widths[l] * 2);
         if (!a.h[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
@@ -70,10 +74,11 @@ smdl_status get_acts(smdl_t h, smdl_prop_t p, int64_t Bpad, bool train, Acts& a)
         const std::string k = std::to_string(l);
         const int wi = p->widths[l], wo = p->widths[l + 1];
         a.hT[l] = (uint16_t*)h->ws(("prop.hT" + k).c_str(), (size_t)Bpad * wi * 2);
-        a.d[l] = (uint16_t*)h->ws(("prop.d" + k).c_str(), (size_t)Bpad * wo * 2);
+        if (a.R == 0) a.d[l] = (uint16_t*)h->ws(("prop.d" + k).c_str(), (size_t)Bpad * wo * 2);
         a.dT[l] = (uint16_t*)h->ws(("prop.dT" + k).c_str(), (size_t)Bpad * wo * 2);
-        a.part[l] = (float*)h->ws(("prop.part" + k).c_str(), (size_t)(Bpad / 32) * wo * 4);
-        if (!a.hT[l] || !a.d[l] || !a.dT[l] || !a.part[l]) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+        a.part[l] = (float*)h->ws(("prop.part" + k).c_str(), (size_t)(Bpad / 16) * wo * 4);
+        if (!a.hT[l] || (a.R == 0 && !a.d[l]) || !a.dT[l] || !a.part[l])
+            return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     }
     return SMDL_OK;
 }
@@ -94,15 +99,13 @@ hipError_t enqueue_forward(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, c
         NtArgs g{};
         g.A = a.h[l];
         g.lda = wi;
-        g.B = p->Wbf[l];
-        g.ldb = wi;
+        g.B = p->Wpk[l];
         g.M = (int)Bpad;
         g.N = wo;
         g.K = wi;
         g.Mvalid = (int)B;
         g.bias = p->b[l];
         g.ldo = wo;
-        g.ldt = (int)Bpad;
         if (l + 1 < L) {
             g.relu = 1;
             g.out_bf16 = a.h[l + 1];
@@ -124,11 +127,9 @@ hipError_t enqueue_forward(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, c
     return hipSuccess;
 }
 
-// Backward pass after a training forward: the deltas of every layer (BF16, transposed, column
-// sums), then one grouped launch for all weight and bias gradients, applied with Adam when
-// `adam` is set (step t) or stored in dW / db.
-hipError_t enqueue_backward(smdl_t h, smdl_prop_t p, int64_t B, Acts& a, const smdl_train_opts* adam, int t_off,
-                            float* const* dW, float* const* db) {
+// Per-layer backward after a training forward: the deltas of every hidden layer (BF16,
+// transposed, column sums over 32-row blocks).
+hipError_t enqueue_deltas(smdl_t h, smdl_prop_t p, int64_t B, Acts& a) {
     const int L = p->n_layers;
     const int64_t Bpad = a.Bpad;
     hipError_t e;
@@ -138,8 +139,7 @@ hipError_t enqueue_backward(smdl_t h, smdl_prop_t p, int64_t B, Acts& a, const s
         NtArgs g{};
         g.A = a.d[l];
         g.lda = wo;
-        g.B = p->WbfT[l];
-        g.ldb = wo;
+        g.B = p->WTpk[l];
         g.M = (int)Bpad;
         g.N = wi;
         g.K = wo;
@@ -149,10 +149,19 @@ hipError_t enqueue_backward(smdl_t h, smdl_prop_t p, int64_t B, Acts& a, const s
         g.out_bf16 = l - 1 >= 1 ? a.d[l - 1] : nullptr;
         g.ldo = wi;
         g.outT = a.dT[l - 1];
-        g.ldt = (int)Bpad;
         g.colpart = a.part[l - 1];
         if ((e = launch_gemm_nt(g, h->stream)) != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+// One grouped launch for all weight and bias gradients (from the transposed activations and
+// deltas and the column sums over blocks of `rows_per_part` rows), applied with Adam when
+// `adam` is set (step t) or stored in dW / db.
+hipError_t enqueue_wgrad(smdl_t h, smdl_prop_t p, Acts& a, int rows_per_part, const smdl_train_opts* adam,
+                         int t_off, float* const* dW, float* const* db) {
+    const int L = p->n_layers;
+    const int64_t Bpad = a.Bpad;
     WgArgs w{};
     w.n_layers = L;
     w.Bpad = (int)Bpad;
@@ -170,7 +179,7 @@ hipError_t enqueue_backward(smdl_t h, smdl_prop_t p, int64_t B, Acts& a, const s
         q.dT = a.dT[l];
         q.hT = a.hT[l];
         q.colpart = a.part[l];
-        q.nparts = (int)(Bpad / 32);
+        q.nparts = (int)(Bpad / rows_per_part);
         q.wo = p->widths[l + 1];
         q.wi = p->widths[l];
         q.W = p->W[l];
@@ -179,12 +188,62 @@ hipError_t enqueue_backward(smdl_t h, smdl_prop_t p, int64_t B, Acts& a, const s
         q.vW = p->vW[l];
         q.mb = p->mb[l];
         q.vb = p->vb[l];
-        q.Wbf = p->Wbf[l];
-        q.WbfT = p->WbfT[l];
+        q.Wpk = p->Wpk[l];
+        q.WTpk = p->WTpk[l];
         q.dW_out = dW ? dW[l] : nullptr;
         q.db_out = db ? db[l] : nullptr;
     }
     return launch_wgrad(w, h->stream);
+}
+
+RowsArgs rows_args(smdl_prop_t p, const float* Y, int64_t B, const int32_t* rows, const Acts& a) {
+    RowsArgs r{};
+    r.Y = Y;
+    r.B = B;
+    r.Bpad = a.Bpad;
+    r.rows = rows;
+    r.n_layers = p->n_layers;
+    for (int l = 0; l <= p->n_layers; ++l) r.w[l] = p->widths[l];
+    for (int l = 0; l < p->n_layers; ++l) {
+        r.W[l] = p->Wpk[l];
+        r.WT[l] = p->WTpk[l];
+        r.bias[l] = p->b[l];
+    }
+    return r;
+}
+
+// Logits of the N rows of Y (B x K FP32 into `logits`).
+hipError_t enqueue_logits(smdl_t h, smdl_prop_t p, const float* Y, int64_t N, Acts& a, float* logits) {
+    if (a.R == 0) return enqueue_forward(h, p, Y, N, nullptr, a, logits, nullptr, 0, nullptr);
+    RowsArgs r = rows_args(p, Y, N, nullptr, a);
+    r.logits = logits;
+    return launch_mlp_rows(r, a.R, h->stream);
+}
+
+// Loss and gradients of a batch of B rows (gathered through `rows`), applied with Adam when
+// `adam` is set, else stored in dW / db.
+hipError_t enqueue_grad_step(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, const int32_t* rows, Acts& a,
+                             const uint32_t* tmask, int tstride, double* loss, const smdl_train_opts* adam,
+                             int t_off, float* const* dW, float* const* db) {
+    hipError_t e;
+    const int K = p->widths[p->n_layers];
+    if (a.R == 0) {
+        if ((e = enqueue_forward(h, p, Y, B, rows, a, nullptr, tmask, tstride, loss)) != hipSuccess) return e;
+        if ((e = enqueue_deltas(h, p, B, a)) != hipSuccess) return e;
+        return enqueue_wgrad(h, p, a, 32, adam, t_off, dW, db);
+    }
+    RowsArgs r = rows_args(p, Y, B, rows, a);
+    r.tmask = tmask;
+    r.tstride = tstride;
+    r.scale = 1.0f / ((float)B * K);
+    r.loss = loss;
+    for (int l = 0; l < p->n_layers; ++l) {
+        r.hT[l] = a.hT[l];
+        r.dT[l] = a.dT[l];
+        r.colpart[l] = a.part[l];
+    }
+    if ((e = launch_mlp_rows(r, a.R, h->stream)) != hipSuccess) return e;
+    return enqueue_wgrad(h, p, a, a.R, adam, t_off, dW, db);
 }
 
 // Multi-hot label bitmask of N samples (workspace), rows of (K + 31) / 32 words.
@@ -234,8 +293,8 @@ extern "C" smdl_status smdl_prop_create(smdl_t h, int n_layers, const int* width
         const size_t nw = (size_t)widths[l] * widths[l + 1], nb = widths[l + 1];
         float *W = p->alloc<float>(nw), *b = p->alloc<float>(nb);
         float *mW = p->alloc<float>(nw), *vW = p->alloc<float>(nw), *mb = p->alloc<float>(nb), *vb = p->alloc<float>(nb);
-        uint16_t *Wbf = p->alloc<uint16_t>(nw), *WbfT = p->alloc<uint16_t>(nw);
-        if (!W || !b || !mW || !vW || !mb || !vb || !Wbf || !WbfT) {
+        uint16_t *Wpk = p->alloc<uint16_t>(nw), *WTpk = p->alloc<uint16_t>(nw);
+        if (!W || !b || !mW || !vW || !mb || !vb || !Wpk || !WTpk) {
             smdl_prop_destroy(p);
             return h->fail(SMDL_E_NOMEM, "proposer allocation failed");
         }
@@ -245,15 +304,15 @@ extern "C" smdl_status smdl_prop_create(smdl_t h, int n_layers, const int* width
         p->vW.push_back(vW);
         p->mb.push_back(mb);
         p->vb.push_back(vb);
-        p->Wbf.push_back(Wbf);
-        p->WbfT.push_back(WbfT);
+        p->Wpk.push_back(Wpk);
+        p->WTpk.push_back(WTpk);
         hipError_t e = hipMemcpyAsync(W, W_init[l], nw * 4, hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(b, b_init[l], nb * 4, hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(mW, 0, nw * 4, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(vW, 0, nw * 4, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(mb, 0, nb * 4, h->stream);
         if (e == hipSuccess) e = hipMemsetAsync(vb, 0, nb * 4, h->stream);
-        if (e == hipSuccess) e = launch_to_bf16(W, (int64_t)nw, widths[l], widths[l + 1], Wbf, WbfT, h->stream);
+        if (e == hipSuccess) e = launch_to_bf16(W, (int64_t)nw, widths[l], widths[l + 1], Wpk, WTpk, h->stream);
         if (e != hipSuccess) {
             smdl_prop_destroy(p);
             return h->hip(e, "proposer init");
@@ -304,8 +363,7 @@ extern "C" smdl_status smdl_prop_logits(smdl_t h, smdl_prop_t p, const float* Y,
     (void)hipSetDevice(h->device);
     Acts a;
     if ((st = get_acts(h, p, pad64b(N), false, a)) != SMDL_OK) return st;
-    if ((st = h->hip(enqueue_forward(h, p, Y, N, nullptr, a, logits, nullptr, 0, nullptr), "forward")) != SMDL_OK)
-        return st;
+    if ((st = h->hip(enqueue_logits(h, p, Y, N, a, logits), "forward")) != SMDL_OK) return st;
     return h->hip(hipStreamSynchronize(h->stream), "forward");
 }
 
@@ -337,9 +395,8 @@ extern "C" smdl_status smdl_prop_grad(smdl_t h, smdl_prop_t p, const float* Y, i
     const uint32_t* tm = label_mask(h, labels, N, K, e);
     if (e != hipSuccess) return h->hip(e, "labels");
     if ((e = launch_zero_f64(dloss, 1, h->stream)) != hipSuccess) return h->hip(e, "grad");
-    if ((e = enqueue_forward(h, p, Y, N, nullptr, a, nullptr, tm, (K + 31) / 32, dloss)) != hipSuccess)
+    if ((e = enqueue_grad_step(h, p, Y, N, nullptr, a, tm, (K + 31) / 32, dloss, nullptr, 0, dW, db)) != hipSuccess)
         return h->hip(e, "grad");
-    if ((e = enqueue_backward(h, p, N, a, nullptr, 0, dW, db)) != hipSuccess) return h->hip(e, "grad");
     double l = 0.0;
     if ((st = h->hip(hipMemcpyAsync(&l, dloss, 8, hipMemcpyDeviceToHost, h->stream), "loss")) != SMDL_OK) return st;
     if ((st = h->hip(hipStreamSynchronize(h->stream), "grad")) != SMDL_OK) return st;
@@ -386,8 +443,8 @@ extern "C" smdl_status smdl_prop_train(smdl_t h, smdl_prop_t p, const float* Y, 
     auto one_epoch = [&]() -> hipError_t {
         hipError_t e2 = launch_zero_f64(eloss, std::max<int64_t>(nb, 1), h->stream);
         for (int64_t bi = 0; bi < nb && e2 == hipSuccess; ++bi) {
-            e2 = enqueue_forward(h, p, Y, B, rows + bi * B, a, nullptr, tm, (K + 31) / 32, eloss + bi);
-            if (e2 == hipSuccess) e2 = enqueue_backward(h, p, B, a, o, (int)bi + 1, nullptr, nullptr);
+            e2 = enqueue_grad_step(h, p, Y, B, rows + bi * B, a, tm, (K + 31) / 32, eloss + bi, o, (int)bi + 1,
+                                   nullptr, nullptr);
         }
         if (e2 == hipSuccess) e2 = launch_add_i32(p->dstep, (int32_t)nb, h->stream);
         return e2;
@@ -483,7 +540,7 @@ extern "C" smdl_status smdl_omp_code_proposed(smdl_t h, smdl_prop_t p, const flo
     if (!cand || !fb_list || !fb_cnt) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     hipError_t e;
     (void)hipEventRecord(h->ev_prop[0], h->stream);
-    if ((e = enqueue_forward(h, p, Y, N, nullptr, a, a.logits, nullptr, 0, nullptr)) != hipSuccess)
+    if ((e = enqueue_logits(h, p, Y, N, a, a.logits)) != hipSuccess)
         return h->hip(e, "forward");
     if ((e = launch_topk(a.logits, N, K, n_cand, cand, h->stream)) != hipSuccess) return h->hip(e, "topk");
     (void)hipEventRecord(h->ev_prop[1], h->stream);

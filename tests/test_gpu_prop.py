@@ -70,6 +70,31 @@ def test_gradient_parity(h, dev):
         assert ew <= REL and eb <= REL
 
 
+def test_wide_network_per_layer_path(h, dev):
+    """A network whose activations do not fit in LDS (64-4096-1024: 5.2 KB per batch row) runs
+    layer by layer; its logits and gradients pass the same bar."""
+    widths = [64, 4096, 1024]
+    Ws, bs = synth.mlp_init(widths, seed=17)
+    D, Y, _ = synth.small_problem(4006, 64, 1024, 8, 0.02, 200)
+    labels = oracle.omp(D, Y, 8)
+    print("case wide network logits", flush=True)
+    p = h.proposer(Ws, bs)
+    lg = p.logits(_t(Y, dev)).cpu().numpy()
+    e = _relfro(lg, oracle.mlp_forward(Ws, bs, Y))
+    print(f"  logits rel {e:.2e}", flush=True)
+    assert e <= REL
+    print("case wide network gradients", flush=True)
+    loss, dW, db = p.grad(_t(Y, dev), _codes_t(labels, dev))
+    lref, dWr, dbr = oracle.mlp_grad(Ws, bs, Y, oracle.multi_hot(labels, 1024))
+    print(f"  loss gpu {loss:.6f} oracle {lref:.6f}", flush=True)
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    for l in range(2):
+        ew, eb = _relfro(dW[l].cpu().numpy(), dWr[l]), _relfro(db[l].cpu().numpy(), dbr[l])
+        print(f"  layer {l}: dW rel {ew:.2e} db rel {eb:.2e}", flush=True)
+        assert ew <= REL and eb <= REL
+    p.close()
+
+
 def test_training_step_and_loss_decrease(h, dev):
     widths = [64, 128, 96, 256]
     Ws, bs = synth.mlp_init(widths, seed=13)
