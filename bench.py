@@ -45,9 +45,10 @@ def omp_bytes_per_signal(m: int, s: int) -> int:
     return 4 * m + 8 * s + 4
 
 
-def measured_traffic():
-    """HBM bytes per launch of the plain OMP pass from the committed rocprofv3 PMC summary, or
-    None when the kernel source has changed since the counters were taken."""
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the plain OMP pass by this kernel instantiation, from the
+    committed rocprofv3 PMC summary; None when that instantiation was not measured or the kernel
+    source has changed since the counters were taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "omp_fused_traffic.json")) as f:
@@ -56,7 +57,32 @@ def measured_traffic():
             sha = hashlib.sha1(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("omp_kernel_sha1") == sha else None
+    if rec.get("omp_kernel_sha1") != sha:
+        return None
+    return rec.get("bytes_per_launch", {}).get(kernel)
+
+
+def train_roofline(widths, samples: int, ms: float):
+    """The proposer training phase (the largest share of the step) against the dense BF16 MFMA
+    peak: forward, hidden deltas and weight gradients are 3 x 2 x sum(w_l w_{l+1}) flops per
+    sample (the first layer's input delta is not formed: 2 x w_0 w_1 less), timed over the whole
+    phase (every launch, the Adam updates and the per-epoch host shuffles included)."""
+    pairs = sum(a * b for a, b in zip(widths[:-1], widths[1:]))
+    f = 6 * pairs - 2 * widths[0] * widths[1]
+    achieved = f * samples / (ms * 1e-3) / 1e12
+    return {"phase": "proposer training (fused network kernel + weight gradients with Adam, per batch)",
+            "bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s", "frac": achieved / 2500.0,
+            "per_sample_flops": f, "samples": samples, "ms": ms}
+
+
+def omp_kernel_name(h, m: int, K: int, s: int) -> str:
+    """The fused OMP instantiation the handle runs for (m, K, s): lanes per signal G, entries per
+    lane EM = Kpad / G, steps SM (the smallest instantiated >= s: 8 for s <= 8), 16 TT signals per
+    item."""
+    lanes, spi = h.get_tile(m, K, s)
+    kpad = (K + 63) // 64 * 64
+    sm = 8 if s <= 8 else (12 if s <= 12 else 16)
+    return f"omp_fused<{kpad // lanes}, {sm}, {lanes}, {spi // 16}>"
 
 
 def cpu_baseline(w, sample_subsets: int, sample_n: int, iters: int):
@@ -87,11 +113,15 @@ def main():
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-subsets", type=int, default=16)
+    ap.add_argument("--cpu-subsets", type=int, default=20)
     ap.add_argument("--cpu-n", type=int, default=5000)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--omp-only", type=int, default=0,
                     help="only run the plain OMP coding of the 100000 signals this many times (for profilers)")
+    ap.add_argument("--omp-tile", default="",
+                    help="with --omp-only: 'lanes,signals_per_item' to force that OMP tile")
+    ap.add_argument("--train-only", type=int, default=0,
+                    help="only train the proposer this many epochs on the 200000 training pairs (for profilers)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -128,10 +158,29 @@ def main():
 
     if args.omp_only:
         D = torch.from_numpy(synth.gaussian_dictionary(np.random.default_rng(1), 64, 256).astype(np.float32)).to(dev)
+        if args.omp_tile:
+            lanes, spi = (int(x) for x in args.omp_tile.split(","))
+            h.set_autotune(False)
+            h.set_tile(256, 8, lanes, spi)
         for _ in range(args.omp_only):
             h.omp_code(D, Y, 8)
         torch.cuda.synchronize()
-        print(json.dumps({"omp_only": args.omp_only, "last_kernel_ms": h.last_kernel_ms()}))
+        print(json.dumps({"omp_only": args.omp_only, "kernel": omp_kernel_name(h, 64, 256, 8),
+                          "last_kernel_ms": h.last_kernel_ms()}))
+        return
+
+    if args.train_only:
+        D = torch.from_numpy(synth.gaussian_dictionary(np.random.default_rng(1), 64, 256).astype(np.float32)).to(dev)
+        labels = h.omp_code(D, Yt, 8)
+        prop = h.proposer(Ws, bs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = prop.train(Yt, labels, epochs=args.train_only, batch=1024, lr=1e-3, shuffle_seed=1)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        prop.close()
+        print(json.dumps({"train_only": args.train_only, "ms": ms, "steps": args.train_only * (Ytr.shape[0] // 1024),
+                          "losses": losses}))
         return
 
     def step():
@@ -144,8 +193,11 @@ def main():
         labels, rn_tr = h.omp_code(D, Yt, 8, res_norm=True)
         rms_tr = torch.sqrt((rn_tr.double() ** 2).mean())
         prop = h.proposer(Ws, bs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         losses = prop.train(Yt, labels, epochs=args.epochs, batch=1024, lr=1e-3, shuffle_seed=1)
         torch.cuda.synchronize()
+        info["train_ms"] = (time.perf_counter() - t0) * 1e3
         t0 = time.perf_counter()
         Xp, rn = h.omp_code(D, Ye, 8, res_norm=True)
         torch.cuda.synchronize()
@@ -197,8 +249,9 @@ def main():
     codings = n_local + w.N + Ytr.shape[0] + 2 * Yev.shape[0]
     value = codings / dt
 
-    # roofline of the dominant kernel: the fused OMP kernel, timed on the plain evaluation pass
+    # roofline of the plain path's kernel: the fused OMP kernel, timed on the plain evaluation pass
     kms = float(np.mean([i["plain_kernel_ms"] for i in infos]))
+    kname = omp_kernel_name(h, 64, 256, 8)
     f_sig = omp_flops_per_signal(64, 256, 8)
     achieved = f_sig * Yev.shape[0] / (kms * 1e-3) / 1e12
     plain_sps = Yev.shape[0] / (kms * 1e-3)
@@ -233,12 +286,15 @@ def main():
         "equal_rmse": None,
         "phase_ms": {"local": last["phase_ms"][0], "merge": last["phase_ms"][1],
                      "final": last["phase_ms"][2], "final_kernel": last["final_kernel_ms"],
+                     "proposer_train": float(np.mean([i["train_ms"] for i in infos])),
                      "plain_eval_kernel": kms, "proposer_net_topk": prop_ms[0],
                      "proposer_restricted": prop_ms[1], "proposer_fallback": prop_ms[2]},
         "train_loss": last["losses"][-1] if last["losses"] else None,
-        "roofline": {"kernel": "omp_fused (plain OMP pass, N=100000)", "bound": "alu",
+        "roofline_proposer_training": train_roofline(widths, Ytr.shape[0] // 1024 * 1024 * args.epochs,
+                                                     float(np.mean([i["train_ms"] for i in infos]))),
+        "roofline": {"kernel": f"{kname} (plain OMP pass, N=100000)", "bound": "alu",
                      "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s", "frac": achieved / 157.3,
-                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch (HBM read + write)",
+                     "traffic": measured_traffic(kname), "traffic_unit": "bytes per launch (HBM read + write)",
                      "per_signal_flops": f_sig,
                      "per_signal_bytes": omp_bytes_per_signal(64, 8)},
     }
