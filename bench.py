@@ -105,6 +105,201 @@ def cpu_baseline(w, sample_subsets: int, sample_n: int, iters: int):
                       f"{iters}+{iters} iterations, final coding of {len(idx)}: {codings} codings in {dt:.2f} s"}
 
 
+def run_batched(args, smdl, synth, torch, dev):
+    """The uneven split phase: 64 subsets of 1000-20000 signals, local K in {64, 128, 192, 256}, s in
+    {4, 8, 12}, 20 iterations, then the merge and the final coding, once with every stage of all
+    subsets in one launch (each iteration a replayed HIP graph) and once with per-subset launches."""
+    w = synth.batched_split(iters=args.iters)
+    Y = torch.from_numpy(w.Y).to(dev)
+    perm = torch.from_numpy(w.perm).to(dev)
+    h = smdl.Handle(0)
+    res = {}
+    for name, flags in (("batched", 0), ("per_subset", smdl.SMDL_PER_SUBSET_LAUNCH)):
+        for _ in range(args.warmup):
+            h.split_merge_learn(Y, perm, w.offsets, w.K_local, w.s_local, w.K, w.iters_local, w.iters_merge,
+                                w.s_merge, w.s_final, flags=flags)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ph = []
+        for _ in range(args.steps):
+            h.split_merge_learn(Y, perm, w.offsets, w.K_local, w.s_local, w.K, w.iters_local, w.iters_merge,
+                                w.s_merge, w.s_final, flags=flags)
+            ph.append(h.phase_ms())
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        local_ms = float(np.mean([p[0] for p in ph]))
+        res[name] = {"ms_per_run": dt * 1e3, "local_ms": local_ms, "merge_ms": float(np.mean([p[1] for p in ph])),
+                     "final_ms": float(np.mean([p[2] for p in ph])),
+                     "local_signals_coded_per_s": w.N * (w.iters_local + 1) / (local_ms * 1e-3)}
+    flops = sum(int(n) * omp_flops_per_signal(64, int(k), int(s_))
+                for n, k, s_ in zip(np.diff(w.offsets), w.K_local, w.s_local))
+    out = {"metric": "signals sparse-coded/sec in the split phase (batched uneven subsets)",
+           "value": res["batched"]["local_signals_coded_per_s"], "unit": "signals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "config": {"workload": w.name, "N": w.N, "L": w.L, "K_local": "64/128/192/256", "s_local": "4/8/12",
+                      "iters_local": w.iters_local, "iters_merge": w.iters_merge},
+           "batched": res["batched"], "per_subset": res["per_subset"],
+           "batched_speedup_local": res["per_subset"]["local_ms"] / res["batched"]["local_ms"],
+           "omp_flops_per_pass": flops,
+           "omp_tflops_local": flops * (w.iters_local + 1) / (res["batched"]["local_ms"] * 1e-3) / 1e12}
+    print(json.dumps(out), flush=True)
+
+
+def run_large(args, smdl, synth, torch, dev):
+    """The large workload: m=256, N=1e6 in 100 uneven subsets, local K=512 s=16 (20 iterations), merge
+    to K=1024 (s=8), final s=16 coding of all N; then the 256-1024-1024-1024 proposer trained on
+    200000 labelled pairs and plain vs proposed coding (48 candidates) of 100000 fresh signals."""
+    w = synth.large_scale(iters=args.iters)
+    Ytr = synth.fresh_signals(w, synth.STREAM_TRAIN, 200000, 16, 0.02)
+    Yev = synth.fresh_signals(w, synth.STREAM_EVAL, 100000, 16, 0.02)
+    print(f"# large workload drawn: N={w.N}, m={w.m}", file=sys.stderr, flush=True)
+    Y = torch.from_numpy(w.Y).to(dev)
+    perm = torch.from_numpy(w.perm).to(dev)
+    Yt = torch.from_numpy(Ytr).to(dev)
+    Ye = torch.from_numpy(Yev).to(dev)
+    h = smdl.Handle(0)
+    widths = [256, 1024, 1024, 1024]
+    Ws, bs = synth.mlp_init(widths)
+
+    def step():
+        info = {}
+        D, X, _, _ = h.split_merge_learn(Y, perm, w.offsets, w.K_local, w.s_local, w.K, w.iters_local,
+                                         w.iters_merge, w.s_merge, w.s_final)
+        info["phase_ms"] = h.phase_ms()
+        labels, rn_tr = h.omp_code(D, Yt, 16, res_norm=True)
+        rms_tr = float(torch.sqrt((rn_tr.double() ** 2).mean()).item())
+        prop = h.proposer(Ws, bs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prop.train(Yt, labels, epochs=args.epochs, batch=1024, lr=1e-3, shuffle_seed=1)
+        torch.cuda.synchronize()
+        info["train_ms"] = (time.perf_counter() - t0) * 1e3
+        Xp = h.omp_code(D, Ye, 16)
+        info["plain_kernel_ms"] = h.last_kernel_ms()
+        Xl, _, nfb, _ = h.omp_code_proposed(prop, D, Ye, 16, 48, 1.1 * rms_tr)
+        torch.cuda.synchronize()
+        info.update(prop_ms=h.prop_phase_ms(), nfb=nfb, D=D, Xp=Xp, Xl=Xl, prop=prop, rms_tr=rms_tr)
+        return info
+
+    for _ in range(args.warmup):
+        step()["prop"].close()
+        print("# warmup step done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(step())
+        if len(infos) > 1:
+            infos[-2]["prop"].close()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    last = infos[-1]
+    D = last["D"]
+
+    def rmse(X):
+        Xd = X.dense(1024).double()
+        R = Ye.double() - Xd @ D.double()
+        return float(torch.sqrt((R ** 2).mean()).item())
+    r_plain, r_learn = rmse(last["Xp"]), rmse(last["Xl"])
+    curve = []
+    for mult in (1.1, 1.0, 0.9, 0.8):
+        Xm, _, nfm, _ = h.omp_code_proposed(last["prop"], D, Ye, 16, 48, mult * last["rms_tr"])
+        torch.cuda.synchronize()
+        curve.append({"eps_mult": mult, "rmse_ratio": rmse(Xm) / r_plain, "fallback_rate": nfm / Yev.shape[0],
+                      "learned_signals_per_s": Yev.shape[0] / (sum(h.prop_phase_ms()) * 1e-3)})
+    last["prop"].close()
+    kms = float(np.mean([i["plain_kernel_ms"] for i in infos]))
+    plain_sps = Yev.shape[0] / (kms * 1e-3)
+    learned_sps = Yev.shape[0] / (sum(last["prop_ms"]) * 1e-3)
+    codings = w.N * (w.iters_local + 1) + w.N + Ytr.shape[0] + 2 * Yev.shape[0]
+    f_final = omp_flops_per_signal(256, 1024, 16)
+    out = {"metric": "signals sparse-coded/sec (m=256,K=1024,s=16), learned vs plain",
+           "value": codings / dt, "unit": "signals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "config": {"workload": w.name + " + proposer_256-1024-1024-1024_top48", "N": w.N, "L": w.L,
+                      "K_local": 512, "s_local": 16, "K": 1024, "s_merge": 8, "s_final": 16,
+                      "iters_local": w.iters_local, "iters_merge": w.iters_merge, "train_pairs": int(Ytr.shape[0]),
+                      "eval_signals": int(Yev.shape[0]), "epochs": args.epochs, "codings_per_step": codings},
+           "phase_ms": {"local": last["phase_ms"][0], "merge": last["phase_ms"][1], "final": last["phase_ms"][2],
+                        "proposer_train": float(np.mean([i["train_ms"] for i in infos])),
+                        "plain_eval_kernel": kms, "proposer_net_topk": last["prop_ms"][0],
+                        "proposer_restricted": last["prop_ms"][1], "proposer_fallback": last["prop_ms"][2]},
+           "plain_signals_per_s": plain_sps, "learned_signals_per_s": learned_sps,
+           "learned_vs_plain": learned_sps / plain_sps, "rmse_ratio": r_learn / r_plain,
+           "fallback_rate": last["nfb"] / Yev.shape[0], "learned_vs_plain_curve": curve,
+           "plain_final_roofline": {"bound": "alu", "per_signal_flops": f_final,
+                                    "achieved": f_final * Yev.shape[0] / (kms * 1e-3) / 1e12, "peak": 157.3,
+                                    "unit": "TFLOP/s", "frac": f_final * Yev.shape[0] / (kms * 1e-3) / 1e12 / 157.3}}
+    print(json.dumps(out), flush=True)
+
+
+def run_e1(args, smdl, synth, torch, dev):
+    """The paper's synthetic experiment (Section 3.1, Table 1) through the library: the standard
+    alternation (K = 60, s = 6) against split-and-merge (40 x 1000, K_1 = 50, s_1 = 3, merged to
+    K = 60 at s_2 = 2, final coding at s = 6) on noise-free signals of a 30 x 60 Gaussian
+    dictionary, averaged over independent trials; the FP64 oracle runs the first trials on the
+    same inputs and is timed beside the GPU."""
+    from paper_1403_4781_amd import evaluate
+    h = smdl.Handle(0)
+    rows = {"standard": [], "split_merge": []}
+    for t in range(args.trials):
+        w = synth.synthetic_e1(t, iters=args.e1_iters)
+        Y = torch.from_numpy(w.Y).to(dev)
+        perm = torch.from_numpy(w.perm).to(dev)
+        for name in ("standard", "split_merge"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "standard":
+                D, X = h.learn(Y, w.K, 6, args.e1_iters)
+            else:
+                D, X, _, _ = h.split_merge_learn(Y, perm, w.offsets, w.K_local, w.s_local, w.K, w.iters_local,
+                                                 w.iters_merge, w.s_merge, w.s_final)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            Dn = D.cpu().numpy()
+            idx, coef, nnz = (a.cpu().numpy() for a in (X.idx, X.coef, X.nnz))
+            rows[name].append({"mse_db": evaluate.mse_db(w.Y, Dn, idx, coef, nnz),
+                               "recovery": evaluate.atom_recovery(w.D0, Dn), "s": sec})
+    ora = {"standard": [], "split_merge": []}
+    if args.e1_oracle_trials > 0:
+        import oracle
+        oracle.build()
+        for t in range(min(args.e1_oracle_trials, args.trials)):
+            w = synth.synthetic_e1(t, iters=args.e1_iters)
+            for name in ("standard", "split_merge"):
+                t0 = time.perf_counter()
+                if name == "standard":
+                    D, X = oracle.learn(w.Y, w.K, 6, args.e1_iters)
+                else:
+                    D, X, _, _ = oracle.split_merge(w.Y, w.perm, w.offsets, w.K_local, w.s_local, w.K,
+                                                    w.iters_local, w.iters_merge, w.s_merge, w.s_final)
+                sec = time.perf_counter() - t0
+                ora[name].append({"mse_db": evaluate.mse_db(w.Y, D, X.idx, X.coef, X.nnz),
+                                  "recovery": evaluate.atom_recovery(w.D0, D), "s": sec})
+
+    def summary(r):
+        if not r:
+            return None
+        return {"mse_db_mean": float(np.mean([x["mse_db"] for x in r])),
+                "mse_db_std": float(np.std([x["mse_db"] for x in r])),
+                "recovery_pct_mean": 100.0 * float(np.mean([x["recovery"] for x in r])),
+                "recovery_pct_std": 100.0 * float(np.std([x["recovery"] for x in r])),
+                "seconds_per_trial": float(np.mean([x["s"] for x in r])), "trials": len(r), "per_trial": r}
+    out = {"metric": "E1: training MSE (dB) and atom recovery (%), standard vs split-and-merge",
+           "config": {"workload": "synthetic_e1 (m=30, K=60, N=40000, s=6, noise-free)", "L": 40, "K_local": 50,
+                      "s_local": 3, "s_merge": 2, "s_final": 6, "iters": args.e1_iters, "trials": args.trials},
+           "gpu": {k: summary(v) for k, v in rows.items()},
+           "oracle": {k: summary(v) for k, v in ora.items()},
+           "oracle_threads": None,
+           "paper_table1": {"standard": {"mse_db": -21.18, "recovery_pct": 94.27, "seconds": 158.16},
+                            "split_merge": {"mse_db": -15.91, "recovery_pct": 85.53, "seconds": 5.95},
+                            "note": "20 trials; the paper states neither its iteration count nor its hardware"}}
+    if args.e1_oracle_trials > 0:
+        import oracle
+        out["oracle_threads"] = oracle.threads()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +317,12 @@ def main():
                     help="with --omp-only: 'lanes,signals_per_item' to force that OMP tile")
     ap.add_argument("--train-only", type=int, default=0,
                     help="only train the proposer this many epochs on the 200000 training pairs (for profilers)")
+    ap.add_argument("--trials", type=int, default=20, help="e1: independent trials")
+    ap.add_argument("--e1-iters", type=int, default=100, help="e1: iterations of every learning stage")
+    ap.add_argument("--e1-oracle-trials", type=int, default=1, help="e1: trials also run by the FP64 oracle")
+    ap.add_argument("--config", default="split_merge", choices=["split_merge", "batched", "large", "e1"],
+                    help="batched: the 64-subset uneven split phase, batched vs per-subset launches; "
+                         "large: m=256, K=1024, N=1e6 with the 256-1024-1024-1024 proposer (one JSON line each)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -134,6 +335,15 @@ def main():
     from paper_1403_4781_amd import synth
 
     dev = torch.device("cuda:0")
+    if args.config == "batched":
+        run_batched(args, smdl, synth, torch, dev)
+        return
+    if args.config == "large":
+        run_large(args, smdl, synth, torch, dev)
+        return
+    if args.config == "e1":
+        run_e1(args, smdl, synth, torch, dev)
+        return
     if args.copy_calib:
         n = args.copy_calib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)

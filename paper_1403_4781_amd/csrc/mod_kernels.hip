@@ -2,16 +2,19 @@
 //
 //  1. csc_count / scan / csc_fill: transpose the ELL codes into per-atom lists of
 //     (signal, coefficient) so that every atom's products can be gathered without atomics
-//     on global memory.
-//  2. mod_products: one block per atom a: column a of A = X X^T (FP64, LDS) and column a of
-//     B = Y X^T (FP64 register accumulation over the atom's list), written below each other as
-//     column a of the augmented matrix M = [A; B] ((Kpad + m) x Kpad, FP64).
+//     on global memory (per-block counts in LDS, one global atomic per atom and block).
+//  2. mod_products: one block per atom a (and per chunk of a long list): column a of
+//     A = X X^T (FP64, LDS) and column a of B = Y X^T (FP64 register accumulation over the
+//     atom's list), written below each other as column a of the augmented matrix
+//     M = [A; B] ((Kpad + m) x Kpad, FP64); the chunks' partial columns are added in order.
 //  3. chol_factor: one block per dictionary: blocked FP64 Cholesky of A with the B rows carried
 //     along (they end as Z = B L^{-T}), MFMA trailing updates, a ridge retry when a pivot is
 //     rejected.  Atoms no signal uses get an identity diagonal (their column of A is zero) and
 //     keep their value.
 //  4. tri_solve: D L = Z by block columns (MFMA products, small triangular blocks), one block
 //     per dictionary; mod_normalize: unit normalisation of the solved atoms.
+#include <algorithm>
+
 #include "smdl_internal.h"
 
 namespace {
@@ -33,21 +36,33 @@ __device__ __forceinline__ int desc_of(const int64_t* __restrict__ starts, int n
 // everywhere and flagged in status[8*t + 3] (the host turns that into SMDL_E_ARG).
 __device__ __forceinline__ int clamp_nnz(int k, int s) { return k < 0 ? 0 : (k > s ? s : k); }
 
-__global__ void csc_count_kernel(const ModDesc* __restrict__ md, int32_t* __restrict__ cnt,
-                                 int32_t* __restrict__ status) {
+// Signals per block of the transpose kernels; each block counts its entries per atom in LDS and
+// touches the global counters once per atom, so that many entries of one atom do not contend.
+constexpr int CSC_SIG = 1024;
+
+__global__ __launch_bounds__(256) void csc_count_kernel(const ModDesc* __restrict__ md, int32_t* __restrict__ cnt,
+                                                        int32_t* __restrict__ status) {
     const ModDesc d = md[blockIdx.y];
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < d.n;
-         n += (int64_t)gridDim.x * blockDim.x) {
+    __shared__ int32_t hist[SMDL_MAX_K];
+    const int tid = threadIdx.x;
+    for (int a = tid; a < d.K; a += 256) hist[a] = 0;
+    __syncthreads();
+    const int64_t n0 = (int64_t)blockIdx.x * CSC_SIG, n1 = min(d.n, n0 + CSC_SIG);
+    bool bad = false;
+    for (int64_t n = n0 + tid; n < n1; n += 256) {
         const int k0 = d.nnz[n];
         const int k = clamp_nnz(k0, d.s_stride);
-        bool bad = k != k0;
+        bad |= k != k0;
         for (int i = 0; i < k; ++i) {
             const int ix = d.idx[n * d.s_stride + i];
             if (ix < 0 || ix >= d.K) { bad = true; continue; }
-            atomicAdd(&cnt[d.atom0 + ix], 1);
+            atomicAdd(&hist[ix], 1);
         }
-        if (bad) atomicOr(&status[8 * blockIdx.y + 3], 1);
     }
+    if (bad) atomicOr(&status[8 * blockIdx.y + 3], 1);
+    __syncthreads();
+    for (int a = tid; a < d.K; a += 256)
+        if (hist[a]) atomicAdd(&cnt[d.atom0 + a], hist[a]);
 }
 
 // Exclusive scan of cnt[0..total) into ptr[0..total]; single block of 1024 threads.
@@ -74,42 +89,73 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ 
     if (threadIdx.x == 1023) ptr[total] = part[1023];
 }
 
-__global__ void csc_fill_kernel(const ModDesc* __restrict__ md, const int32_t* __restrict__ ptr,
-                                int32_t* __restrict__ fill, int32_t* __restrict__ list_sig,
-                                float* __restrict__ list_coef) {
+// Each block reserves one contiguous range per atom in that atom's list (one global atomic per
+// atom with entries in the block), then places its entries through LDS cursors.
+__global__ __launch_bounds__(256) void csc_fill_kernel(const ModDesc* __restrict__ md, const int32_t* __restrict__ ptr,
+                                                       int32_t* __restrict__ fill, int32_t* __restrict__ list_sig,
+                                                       float* __restrict__ list_coef) {
     const ModDesc d = md[blockIdx.y];
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < d.n;
-         n += (int64_t)gridDim.x * blockDim.x) {
+    __shared__ int32_t base[SMDL_MAX_K];
+    __shared__ int32_t cur[SMDL_MAX_K];
+    const int tid = threadIdx.x;
+    for (int a = tid; a < d.K; a += 256) cur[a] = 0;
+    __syncthreads();
+    const int64_t n0 = (int64_t)blockIdx.x * CSC_SIG, n1 = min(d.n, n0 + CSC_SIG);
+    for (int64_t n = n0 + tid; n < n1; n += 256) {
+        const int k = clamp_nnz(d.nnz[n], d.s_stride);
+        for (int i = 0; i < k; ++i) {
+            const int ix = d.idx[n * d.s_stride + i];
+            if (ix >= 0 && ix < d.K) atomicAdd(&cur[ix], 1);
+        }
+    }
+    __syncthreads();
+    for (int a = tid; a < d.K; a += 256) {
+        const int c = cur[a];
+        base[a] = c ? ptr[d.atom0 + a] + atomicAdd(&fill[d.atom0 + a], c) : 0;
+        cur[a] = 0;
+    }
+    __syncthreads();
+    for (int64_t n = n0 + tid; n < n1; n += 256) {
         const int k = clamp_nnz(d.nnz[n], d.s_stride);
         for (int i = 0; i < k; ++i) {
             const int ix = d.idx[n * d.s_stride + i];
             if (ix < 0 || ix >= d.K) continue;
-            const int64_t ga = d.atom0 + ix;
-            const int pos = ptr[ga] + atomicAdd(&fill[ga], 1);
+            const int pos = base[ix] + atomicAdd(&cur[ix], 1);
             list_sig[pos] = (int32_t)n;
             list_coef[pos] = d.coef[n * d.s_stride + i];
         }
     }
 }
 
-// One block per (atom a, descriptor).  Writes column a of M = [A; B] (FP64).
+// One block per (atom a, descriptor, chunk c): the products over chunk c of the P equal parts of
+// atom a's list.  Chunk 0 writes column a of M = [A; B] (FP64) in place; chunk c > 0 writes the
+// same column of copy c - 1 of the M arena in `part` (sum_reduce_kernel adds the copies in a
+// fixed order).  Long lists (many signals per atom) are so spread over P blocks.
 __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __restrict__ md, int m,
                                                            const int32_t* __restrict__ ptr,
                                                            const int32_t* __restrict__ list_sig,
-                                                           const float* __restrict__ list_coef) {
+                                                           const float* __restrict__ list_coef,
+                                                           const double* __restrict__ arena, double* __restrict__ part,
+                                                           int64_t arena_len) {
     const ModDesc d = md[blockIdx.y];
     const int a = blockIdx.x;
+    const int c = blockIdx.z, P = gridDim.z;
     if (a >= d.Kpad) return;
     __shared__ double colA[SMDL_MAX_K];
-    __shared__ double partB[4][SMDL_MAX_M];
+    __shared__ double partB[8][SMDL_MAX_M];
     const int tid = threadIdx.x;
     for (int l = tid; l < d.Kpad; l += 256) colA[l] = 0.0;
     __syncthreads();
     const int64_t ld = d.Kpad + m;
-    double* out = d.A + (int64_t)a * ld;
+    double* out = (c == 0 ? d.A : part + (int64_t)(c - 1) * arena_len + (d.A - arena)) + (int64_t)a * ld;
+    const int mcov = m <= 32 ? 32 : (m <= 64 ? 64 : (m <= 128 ? 128 : 256));
+    const int groups = 256 / mcov;
+    const int r = tid % mcov, grp = tid / mcov;
     if (a < d.K) {
         const int64_t ga = d.atom0 + a;
-        const int b = ptr[ga], e = ptr[ga + 1];
+        const int lb = ptr[ga], le = ptr[ga + 1];
+        const int len = (le - lb + P - 1) / P;
+        const int b = min(le, lb + c * len), e = min(le, b + len);
         // A column: every entry (n, x_na) adds x_na * x_nl at every atom l of signal n
         for (int p = b + tid; p < e; p += 256) {
             const int64_t n = list_sig[p];
@@ -122,11 +168,9 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
             }
         }
         // B column: rows split over threads, entries over groups of threads
-        const int mcov = m <= 64 ? 64 : (m <= 128 ? 128 : 256);
-        const int groups = 256 / mcov;
-        const int r = tid % mcov, grp = tid / mcov;
         double acc = 0.0;
         if (r < m) {
+#pragma unroll 4
             for (int p = b + grp; p < e; p += groups) {
                 const int64_t n = list_sig[p];
                 acc += (double)list_coef[p] * (double)d.Y[n * m + r];
@@ -134,17 +178,23 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
         }
         partB[grp][r] = acc;
     } else {
-        const int mcov = m <= 64 ? 64 : (m <= 128 ? 128 : 256);
-        partB[tid / mcov][tid % mcov] = 0.0;
+        partB[grp][r] = 0.0;
     }
     __syncthreads();
     for (int l = tid; l < d.Kpad; l += 256) out[l] = colA[l];
-    const int mcov = m <= 64 ? 64 : (m <= 128 ? 128 : 256);
-    const int groups = 256 / mcov;
-    for (int r = tid; r < m; r += 256) {
-        double s = 0.0;
-        for (int q = 0; q < groups; ++q) s += partB[q][r];
-        out[d.Kpad + r] = s;
+    for (int rr = tid; rr < m; rr += 256) {
+        double sm = 0.0;
+        for (int q = 0; q < groups; ++q) sm += partB[q][rr];
+        out[d.Kpad + rr] = sm;
+    }
+}
+
+// arena[f] += sum_{c < P - 1} part[c * len + f], in order of c.
+__global__ void sum_reduce_kernel(double* __restrict__ arena, const double* __restrict__ part, int64_t len, int nparts) {
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < len; f += (int64_t)gridDim.x * blockDim.x) {
+        double v = arena[f];
+        for (int c = 0; c < nparts; ++c) v += part[(int64_t)c * len + f];
+        arena[f] = v;
     }
 }
 
@@ -514,33 +564,31 @@ __global__ __launch_bounds__(256) void mod_normalize_kernel(const ModDesc* __res
     for (int r = lane; r < m; r += 64) d.D[(int64_t)j * m + r] = (float)(col[r] * inv);
 }
 
-inline int grid_sig(int64_t n) {
-    int64_t g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
-    return (int)(g < 1 ? 1 : g);
-}
-
 }  // namespace
 
-hipError_t launch_mod(const ModDesc* dev_desc, const ModDesc* host_desc, int n_desc, int m,
-                      int total_atoms, int64_t max_n, int32_t* cnt, int32_t* fill, int32_t* ptr,
-                      int32_t* list_sig, float* list_coef, int32_t* status, int max_kpad,
-                      hipStream_t st, bool /*per_desc*/) {
-    (void)host_desc;
+hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atoms, int64_t max_n, int32_t* cnt,
+                      int32_t* fill, int32_t* ptr, int32_t* list_sig, float* list_coef, int32_t* status,
+                      int max_kpad, double* arena, double* part, int64_t arena_len, int chunks, hipStream_t st) {
     hipError_t e;
+    if (chunks < 1 || (chunks > 1 && !part)) return hipErrorInvalidValue;
     if ((e = launch_zero_i32(cnt, total_atoms, st)) != hipSuccess) return e;
     if ((e = launch_zero_i32(fill, total_atoms, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(csc_count_kernel, dim3(grid_sig(max_n), n_desc), dim3(256), 0, st, dev_desc, cnt,
-                       status);
+    const unsigned csc_blocks = (unsigned)std::max<int64_t>(1, (max_n + CSC_SIG - 1) / CSC_SIG);
+    hipLaunchKernelGGL(csc_count_kernel, dim3(csc_blocks, n_desc), dim3(256), 0, st, dev_desc, cnt, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, cnt, total_atoms, ptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(csc_fill_kernel, dim3(grid_sig(max_n), n_desc), dim3(256), 0, st, dev_desc, ptr,
+    hipLaunchKernelGGL(csc_fill_kernel, dim3(csc_blocks, n_desc), dim3(256), 0, st, dev_desc, ptr,
                        fill, list_sig, list_coef);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(mod_products_kernel, dim3(max_kpad, n_desc), dim3(256), 0, st, dev_desc, m, ptr,
-                       list_sig, list_coef);
+    hipLaunchKernelGGL(mod_products_kernel, dim3(max_kpad, n_desc, chunks), dim3(256), 0, st, dev_desc, m, ptr,
+                       list_sig, list_coef, arena, part, arena_len);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (chunks > 1) {
+        const unsigned g = (unsigned)std::min<int64_t>(4096, (arena_len + 255) / 256);
+        hipLaunchKernelGGL(sum_reduce_kernel, dim3(g), dim3(256), 0, st, arena, part, arena_len, chunks - 1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(tri_solve_kernel, dim3(n_desc), dim3(TCS), 0, st, dev_desc, m, status);

@@ -431,8 +431,15 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
     plan.list_coef = (float*)h->ws((t + ".lc").c_str(), std::max<int64_t>(1, entries) * 4);
     plan.status = (int32_t*)h->ws((t + ".status").c_str(), 8 * specs.size() * 4);
     plan.desc = (ModDesc*)h->ws((t + ".md").c_str(), specs.size() * sizeof(ModDesc));
+    // products: about 512 list entries per block; long lists (many signals per atom) are split
+    int64_t per_atom = 0;
+    for (auto& s : specs) per_atom = std::max<int64_t>(per_atom, (s.n * s.s_stride + s.K - 1) / s.K);
+    plan.chunks = (int)std::min<int64_t>(16, std::max<int64_t>(1, (per_atom + 511) / 512));
+    plan.arena = A;
+    plan.arena_len = (int64_t)(abytes / 8);
+    plan.part = plan.chunks > 1 ? (double*)h->ws((t + ".part").c_str(), abytes * (plan.chunks - 1)) : nullptr;
     if (!A || !W || !plan.cnt || !plan.fill || !plan.ptr || !plan.list_sig || !plan.list_coef ||
-        !plan.status || !plan.desc)
+        !plan.status || !plan.desc || (plan.chunks > 1 && !plan.part))
         return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     std::vector<ModDesc> md(specs.size());
     size_t ao = 0;
@@ -452,9 +459,9 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
 }
 
 hipError_t enqueue_mod(smdl_t h, const ModPlan& plan) {
-    return launch_mod(plan.desc, nullptr, plan.n_desc, plan.m, plan.total_atoms, plan.max_n, plan.cnt,
-                      plan.fill, plan.ptr, plan.list_sig, plan.list_coef, plan.status, plan.maxKpad,
-                      h->stream, false);
+    return launch_mod(plan.desc, plan.n_desc, plan.m, plan.total_atoms, plan.max_n, plan.cnt, plan.fill, plan.ptr,
+                      plan.list_sig, plan.list_coef, plan.status, plan.maxKpad, plan.arena, plan.part,
+                      plan.arena_len, plan.chunks, h->stream);
 }
 
 // Read the MOD status array; returns SMDL_E_NUMERIC / SMDL_E_ARG on failures.

@@ -91,6 +91,9 @@ struct ModPlan {
     ModDesc* desc = nullptr;
     int32_t *cnt = nullptr, *fill = nullptr, *ptr = nullptr, *list_sig = nullptr, *status = nullptr;
     float* list_coef = nullptr;
+    double *arena = nullptr, *part = nullptr;   // products workspace and its partial copies
+    int64_t arena_len = 0;                      // doubles
+    int chunks = 1;                             // blocks per atom in the products
     std::vector<ModDesc> host_desc;
 };
 

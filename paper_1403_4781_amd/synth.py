@@ -189,6 +189,18 @@ def large_scale(N: int = 1000000, L: int = 100, iters: int = 20) -> Workload:
                          iters_local=iters, iters_merge=iters, s_merge=8, s_final=16)
 
 
+def synthetic_e1(trial: int, iters: int = 100, N: int = 40000) -> Workload:
+    """The paper's synthetic experiment (Section 3.1, Table 1), trial ``trial``: a 30 x 60 Gaussian
+    dictionary with unit atoms, N = 4 x 10^4 noise-free signals of 6 atoms with N(0, 1) weights;
+    split-and-merge with L = 40 subsets of 1000, local K_1 = 50 at s_1 = 3, merged to K = 60 at
+    s_2 = 2, and the final coding at s = 6.  The standard approach learns K = 60 at s = 6 from the
+    first 60 training vectors.  The paper does not state the iteration count; ``iters`` serves
+    every learning stage."""
+    return make_workload(f"e1_trial{trial}", seed=SEED_BASE + 100 + trial, m=30, K0=60, s0=6, sigma=0.0,
+                         N=N, sizes=equal_sizes(N, 40), K_local=50, s_local=3, K=60,
+                         iters_local=iters, iters_merge=iters, s_merge=2, s_final=6)
+
+
 def fresh_signals(w: Workload, stream: int, N: int, s0: int, sigma: float) -> np.ndarray:
     """Fresh signals from the same generating dictionary as workload ``w``
     (training pairs use STREAM_TRAIN, evaluation signals STREAM_EVAL)."""
