@@ -241,25 +241,28 @@ def run_e1(args, smdl, synth, torch, dev):
     same inputs and is timed beside the GPU."""
     from paper_1403_4781_amd import evaluate
     h = smdl.Handle(0)
-    rows = {"standard": [], "split_merge": []}
+    rows = {"standard": [], "split_merge": [], "split_merge_composed": []}
     for t in range(args.trials):
         w = synth.synthetic_e1(t, iters=args.e1_iters)
         Y = torch.from_numpy(w.Y).to(dev)
         perm = torch.from_numpy(w.perm).to(dev)
-        for name in ("standard", "split_merge"):
+        for name in rows:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if name == "standard":
                 D, X = h.learn(Y, w.K, 6, args.e1_iters)
             else:
+                # the composed form (Proposition 1) replaces the final coding by X = Z X1
+                flags = smdl.SMDL_COMPOSE_CODES if name == "split_merge_composed" else 0
                 D, X, _, _ = h.split_merge_learn(Y, perm, w.offsets, w.K_local, w.s_local, w.K, w.iters_local,
-                                                 w.iters_merge, w.s_merge, w.s_final)
+                                                 w.iters_merge, w.s_merge, w.s_final, flags=flags)
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
             Dn = D.cpu().numpy()
             idx, coef, nnz = (a.cpu().numpy() for a in (X.idx, X.coef, X.nnz))
             rows[name].append({"mse_db": evaluate.mse_db(w.Y, Dn, idx, coef, nnz),
-                               "recovery": evaluate.atom_recovery(w.D0, Dn), "s": sec})
+                               "recovery": evaluate.atom_recovery(w.D0, Dn), "s": sec,
+                               "mean_nnz": float(nnz.mean())})
     ora = {"standard": [], "split_merge": []}
     if args.e1_oracle_trials > 0:
         import oracle
@@ -284,7 +287,8 @@ def run_e1(args, smdl, synth, torch, dev):
                 "mse_db_std": float(np.std([x["mse_db"] for x in r])),
                 "recovery_pct_mean": 100.0 * float(np.mean([x["recovery"] for x in r])),
                 "recovery_pct_std": 100.0 * float(np.std([x["recovery"] for x in r])),
-                "seconds_per_trial": float(np.mean([x["s"] for x in r])), "trials": len(r), "per_trial": r}
+                "seconds_per_trial": float(np.mean([x["s"] for x in r])), "trials": len(r),
+                "mean_nnz": float(np.mean([x.get("mean_nnz", 0.0) for x in r])), "per_trial": r}
     out = {"metric": "E1: training MSE (dB) and atom recovery (%), standard vs split-and-merge",
            "config": {"workload": "synthetic_e1 (m=30, K=60, N=40000, s=6, noise-free)", "L": 40, "K_local": 50,
                       "s_local": 3, "s_merge": 2, "s_final": 6, "iters": args.e1_iters, "trials": args.trials},

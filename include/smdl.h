@@ -135,13 +135,15 @@ typedef struct {
 
 #define SMDL_PER_SUBSET_LAUNCH 1u   /* launch each subset's kernels separately (comparison)  */
 #define SMDL_NO_GRAPH 2u            /* do not capture/replay the iteration as a HIP graph    */
+#define SMDL_COMPOSE_CODES 4u       /* X_out = the Proposition 1 composition Z X1 (see below)
+                                       instead of a fresh OMP of all N signals               */
 
 typedef struct {
     int iters_local;   /* alternations on every subset (step 2)                               */
     int iters_merge;   /* alternations of the merge (step 3)                                  */
     int s_merge;       /* sparsity of the merge (step 3, s2)                                  */
     int s_final;       /* sparsity of the final coding of all N signals                       */
-    uint32_t flags;    /* SMDL_PER_SUBSET_LAUNCH | SMDL_NO_GRAPH                               */
+    uint32_t flags;    /* SMDL_PER_SUBSET_LAUNCH | SMDL_NO_GRAPH | SMDL_COMPOSE_CODES          */
 } smdl_learn_opts;
 
 /*
@@ -163,6 +165,26 @@ smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, int64_t N,
                                    const smdl_subsets* sub, int K, const smdl_learn_opts* o,
                                    float* D_out, smdl_codes X_out, float* D_local_out,
                                    double* scales_out);
+
+/*
+ * Proposition 1 (proof in Appendix A) applied to the codes of Algorithm 1.  A signal of subset t
+ * with local code x1 (over D^(t)) is represented over the merged D by
+ *     r = sum_i (x1_i / c_t) z_{a_i},
+ * where a_i = sum_{u<t} K_local[u] + (local atom of entry i) is its pooled column of
+ * Ytilde = [c_1 D^(1), ..., c_L D^(L)], z_a that column's merge code and c_t = ||X^(t)||_F.
+ * At most X1.s_max * Z.s_max atoms; equal atoms are added (FP64); distinct atoms in order of
+ * first occurrence (local entry, then merge entry); unused slots (-1, 0).
+ *   X1: device, N rows in split order (position p of subset t = offsets[t] + ...), local atom ids
+ *   Z:  device, sum(K_local) rows (pooled columns, subsets in order), atom ids of D (0..K-1)
+ *   scales: host double[L];  sub: L, offsets (host), K_local (host), perm (device, position p ->
+ *   output row perm[p]; NULL = identity); s_local is not read.
+ *   X_out: device, N rows; X1.s_max * Z.s_max <= X_out.s_max <= 64.
+ * smdl_split_merge_learn with SMDL_COMPOSE_CODES runs this on its own local codes (the final codes
+ * of step 2) and merge codes (a final coding of Ytilde with D), in place of the fresh coding;
+ * s_final is then unused and X_out.s_max must be in [max_t s_local[t] * s_merge, 64].
+ */
+smdl_status smdl_compose_codes(smdl_t h, int64_t N, const smdl_subsets* sub, smdl_codes X1, smdl_codes Z,
+                               int K, const double* scales, smdl_codes X_out);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Learned support proposer                                                                 */

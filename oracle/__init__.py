@@ -265,6 +265,30 @@ def multi_hot(codes: Codes, K: int) -> np.ndarray:
     return T
 
 
+def compose_codes(X1: Codes, offsets, K_local, Z: Codes, scales, K: int, perm=None) -> np.ndarray:
+    """Proposition 1 (proof in Appendix A) on Algorithm 1's codes, written out densely in FP64:
+    y ~ Dtilde x1 with Dtilde = [c_1 D^(1), ..., c_L D^(L)] and Dtilde ~ D Z give y ~ D (Z x1).
+    X1 holds each signal's code over its unscaled local dictionary D^(t) (rows in split order,
+    local atom ids), so over Dtilde the code is x1 / c_t.  Z holds the codes of the pooled
+    columns over D.  Returns R (N x K): row perm[p] = Z (x1_p / c_t) for position p of subset t."""
+    offsets = np.asarray(offsets, np.int64)
+    K_local = np.asarray(K_local, np.int64)
+    aoff = np.concatenate([[0], np.cumsum(K_local)])
+    N = int(offsets[-1])
+    Zd = Z.dense(K)                                   # (sum K_local, K): row a = z_a
+    R = np.zeros((N, K))
+    for t in range(len(K_local)):
+        if not scales[t] > 0:
+            continue
+        for p in range(int(offsets[t]), int(offsets[t + 1])):
+            x = np.zeros(int(K_local[t]))
+            for i in range(int(X1.nnz[p])):
+                x[X1.idx[p, i]] += X1.coef[p, i]
+            r = (x / scales[t]) @ Zd[aoff[t]:aoff[t + 1]]
+            R[perm[p] if perm is not None else p] = r
+    return R
+
+
 def tie_mask(codes: Codes, eps: float = 0.0, margin: float = 1e-5, tau: float = TAU,
              dep_tol: float = DEP_TOL) -> np.ndarray:
     """Signals whose FP64 trace comes close to a decision boundary (excluded from

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsmdl.so"
 
 SMDL_PER_SUBSET_LAUNCH = 1
 SMDL_NO_GRAPH = 2
+SMDL_COMPOSE_CODES = 4
 
 _STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_UNSUPPORTED", -4: "E_NOMEM", -5: "E_HIP",
            -6: "E_NUMERIC", -7: "E_STATE"}
@@ -71,6 +72,7 @@ def _load():
         "smdl_learn": [vp, vp, i32, i64, i32, i32, i32, vp, _Codes],
         "smdl_split_merge_learn": [vp, vp, i32, i64, C.POINTER(_Subsets), i32, C.POINTER(_LearnOpts), vp,
                                    _Codes, vp, C.POINTER(C.c_double)],
+        "smdl_compose_codes": [vp, i64, C.POINTER(_Subsets), _Codes, _Codes, i32, C.POINTER(C.c_double), _Codes],
         "smdl_prop_create": [vp, i32, C.POINTER(C.c_int), C.POINTER(C.POINTER(C.c_float)),
                              C.POINTER(C.POINTER(C.c_float)), C.POINTER(vp)],
         "smdl_prop_destroy": [vp],
@@ -246,13 +248,33 @@ class Handle:
                        s_local.ctypes.data_as(C.POINTER(C.c_int32)))
         opts = _LearnOpts(iters_local, iters_merge, s_merge, s_final, flags)
         D = torch.empty((K, m), dtype=torch.float32, device=Y.device)
-        X = Codes.empty(N, s_final, Y.device) if codes else None
-        xc = X._c() if X is not None else _Codes(None, None, None, s_final)
+        s_out = int(s_local.max()) * s_merge if flags & SMDL_COMPOSE_CODES else s_final
+        X = Codes.empty(N, s_out, Y.device) if codes else None
+        xc = X._c() if X is not None else _Codes(None, None, None, s_out)
         Dl = torch.empty((int(K_local.sum()), m), dtype=torch.float32, device=Y.device) if local else None
         scales = np.zeros(L, dtype=np.float64)
         self._check(lib().smdl_split_merge_learn(self._h, _ptr(Y), m, N, C.byref(sub), K, C.byref(opts), _ptr(D),
                                                xc, _ptr(Dl), scales.ctypes.data_as(C.POINTER(C.c_double))))
         return D, X, Dl, scales
+
+    def compose_codes(self, X1: "Codes", Z: "Codes", offsets, K_local, K: int, scales, perm: torch.Tensor | None = None):
+        """Proposition 1 composition (see smdl_compose_codes): codes over D with at most
+        X1.s * Z.s atoms per signal."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        K_local = np.ascontiguousarray(K_local, dtype=np.int32)
+        scales = np.ascontiguousarray(scales, dtype=np.float64)
+        L = len(K_local)
+        N = int(offsets[-1])
+        if perm is not None:
+            _dev_tensor(perm, torch.int64, "perm", (N,))
+        s_l = np.zeros(L, np.int32)
+        sub = _Subsets(L, _ptr(perm).value if perm is not None else None,
+                       offsets.ctypes.data_as(C.POINTER(C.c_int64)), K_local.ctypes.data_as(C.POINTER(C.c_int32)),
+                       s_l.ctypes.data_as(C.POINTER(C.c_int32)))
+        X = Codes.empty(N, X1.idx.shape[1] * Z.idx.shape[1], X1.idx.device)
+        self._check(lib().smdl_compose_codes(self._h, N, C.byref(sub), X1._c(), Z._c(), K,
+                                             scales.ctypes.data_as(C.POINTER(C.c_double)), X._c()))
+        return X
 
     def phase_ms(self):
         v = (C.c_float * 3)()

@@ -163,6 +163,76 @@ __global__ void pool_scale_kernel(const float* __restrict__ Dloc, const int64_t*
     }
 }
 
+// Proposition 1 (Appendix A) on the codes of Algorithm 1: a signal of subset t with local code
+// x1 over D^(t) gets r = sum_i (x1_i / c_t) z_{a_i}, where z_a is the merge code of pooled column
+// a = aoff[t] + (local atom) of Ytilde = [c_t D^(t)] and c_t = ||X^(t)||_F.  One wave per signal
+// position p (local codes are in subset order, the output row is perm[p]); lane j = i * ms + k
+// takes local entry i and merge entry k.  Equal atoms are combined (FP64, in lane order); the
+// distinct atoms are written in order of first occurrence, the unused slots as (-1, 0).
+__global__ __launch_bounds__(256) void compose_codes_kernel(
+    const int32_t* __restrict__ lidx, const float* __restrict__ lcoef, const int32_t* __restrict__ lnnz, int ls,
+    const int32_t* __restrict__ midx, const float* __restrict__ mcoef, const int32_t* __restrict__ mnnz, int ms,
+    const int64_t* __restrict__ offs, const int64_t* __restrict__ aoff, int L, const double* __restrict__ scales,
+    const int64_t* __restrict__ perm, int64_t N, int K, int32_t* __restrict__ oidx, float* __restrict__ ocoef,
+    int32_t* __restrict__ onnz, int os, int32_t* __restrict__ bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= N) return;                              // uniform per wave
+    const int64_t n = perm ? perm[p] : p;
+    if (n < 0 || n >= N) {                           // not a permutation entry: flagged, nothing written
+        if (lane == 0) atomicOr(bad, 1);
+        return;
+    }
+    int lo = 0, hi = L - 1;
+    while (lo < hi) {                                // subset t with offs[t] <= p < offs[t + 1]
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    const int t = lo;
+    const int Kt = (int)(aoff[t + 1] - aoff[t]);
+    const double c = scales[t];
+    const int i = lane / ms, k = lane - i * ms;
+    int atom = -1;
+    double val = 0.0;
+    const int k1 = lnnz[p];
+    if (i < ls && i < k1 && c > 0.0) {
+        const int la = lidx[p * ls + i];
+        if (la >= 0 && la < Kt) {
+            const int64_t a = aoff[t] + la;
+            const int k2 = mnnz[a];
+            if (k < k2) {
+                const int ma = midx[a * ms + k];
+                if (ma >= 0 && ma < K) {
+                    atom = ma;
+                    val = (double)lcoef[p * ls + i] * (double)mcoef[a * ms + k] / c;
+                }
+            }
+        }
+    }
+    double sum = 0.0;
+    bool first = atom >= 0;
+    for (int q = 0; q < ls * ms; ++q) {
+        const int oa = __shfl(atom, q, 64);
+        const double ov = __shfl(val, q, 64);
+        if (atom >= 0 && oa == atom) {
+            sum += ov;
+            if (q < lane) first = false;
+        }
+    }
+    const uint64_t firsts = __ballot(first);
+    const int cnt = __popcll(firsts);
+    const int rank = __popcll(firsts & ((1ull << lane) - 1ull));
+    if (first) {
+        oidx[n * os + rank] = atom;
+        ocoef[n * os + rank] = (float)sum;
+    }
+    if (lane >= cnt && lane < os) {
+        oidx[n * os + lane] = -1;
+        ocoef[n * os + lane] = 0.f;
+    }
+    if (lane == 0) onnz[n] = cnt;
+}
+
 __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -224,6 +294,18 @@ hipError_t launch_code_scales(const float* coef, const int32_t* nnz, int s_strid
                               const int64_t* offsets_dev, int L, double* scales, hipStream_t st) {
     hipLaunchKernelGGL(code_scales_kernel, dim3(L), dim3(256), 0, st, coef, nnz, s_stride,
                        offsets_dev, scales);
+    return hipGetLastError();
+}
+
+hipError_t launch_compose_codes(const int32_t* lidx, const float* lcoef, const int32_t* lnnz, int ls,
+                                const int32_t* midx, const float* mcoef, const int32_t* mnnz, int ms,
+                                const int64_t* offs_dev, const int64_t* aoff_dev, int L, const double* scales,
+                                const int64_t* perm, int64_t N, int K, int32_t* oidx, float* ocoef, int32_t* onnz,
+                                int os, int32_t* bad, hipStream_t st) {
+    if (N <= 0) return hipSuccess;
+    if (ls < 1 || ms < 1 || ls * ms > 64 || os < ls * ms || os > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(compose_codes_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, lidx, lcoef, lnnz, ls,
+                       midx, mcoef, mnnz, ms, offs_dev, aoff_dev, L, scales, perm, N, K, oidx, ocoef, onnz, os, bad);
     return hipGetLastError();
 }
 

@@ -701,7 +701,15 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
     }
     if (sumK < K) return h->fail(SMDL_E_ARG, "the pooled local atoms must number at least K");
     if (sumK * 16 > INT32_MAX) return h->fail(SMDL_E_SHAPE, "too many pooled atoms");
-    if (X_out.idx && (st = check_codes(h, X_out, N, o->s_final)) != SMDL_OK) return st;
+    const bool compose = (o->flags & SMDL_COMPOSE_CODES) != 0;
+    if (X_out.idx && !compose && (st = check_codes(h, X_out, N, o->s_final)) != SMDL_OK) return st;
+    if (X_out.idx && compose) {
+        if (!X_out.coef || !X_out.nnz) return h->fail(SMDL_E_ARG, "null code array");
+        if (s_loc_max * o->s_merge > SMDL_MAX_COMPOSED)
+            return h->fail(SMDL_E_SHAPE, "composed codes need s_local * s_merge <= 64");
+        if (X_out.s_max < s_loc_max * o->s_merge || X_out.s_max > SMDL_MAX_COMPOSED)
+            return h->fail(SMDL_E_ARG, "composed codes need s_local * s_merge <= codes.s_max <= 64");
+    }
     (void)hipSetDevice(h->device);
 
     // step 1: the subsets as contiguous blocks of a permuted copy of Y
@@ -772,11 +780,23 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
     ms[0].s = o->s_merge;
     ms[0].D = D_out;
     ms[0].out0 = 0;
-    if ((st = learn_sets(h, m, ms, o->iters_merge, mc, false, o->flags & SMDL_NO_GRAPH, "sm.mrg")) != SMDL_OK) return st;
+    if ((st = learn_sets(h, m, ms, o->iters_merge, mc, compose && X_out.idx, o->flags & SMDL_NO_GRAPH, "sm.mrg")) !=
+        SMDL_OK)
+        return st;
     auto t2 = std::chrono::steady_clock::now();
 
-    // final coding of all N signals (original order)
-    if (X_out.idx) {
+    if (X_out.idx && compose) {
+        // Proposition 1: X = Z X1 from the local codes and the merge codes (no fresh coding)
+        // (perm was checked by the gather of step 1)
+        int32_t* bad = (int32_t*)h->ws("sm.cbad", 64);
+        if (!bad) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+        if ((st = h->hip(launch_compose_codes(lc.idx, lc.coef, lc.nnz, lc.s_stride, mc.idx, mc.coef, mc.nnz, mc.s_stride,
+                                              offs_dev, aoff_dev, L, scales, sub->perm, N, K, X_out.idx, X_out.coef,
+                                              X_out.nnz, X_out.s_max, bad, h->stream),
+                         "compose")) != SMDL_OK)
+            return st;
+    } else if (X_out.idx) {
+        // final coding of all N signals (original order)
         if ((st = omp_code_impl(h, D_out, m, K, Y, N, o->s_final, 0.f, X_out, nullptr, nullptr, nullptr, 0,
                                 "sm.fin")) != SMDL_OK)
             return st;
@@ -792,6 +812,54 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
     h->phase_ms[1] = std::chrono::duration<float, std::milli>(t2 - t1).count();
     h->phase_ms[2] = std::chrono::duration<float, std::milli>(t3 - t2).count();
     return st;
+}
+
+extern "C" smdl_status smdl_compose_codes(smdl_t h, int64_t N, const smdl_subsets* sub, smdl_codes X1, smdl_codes Z,
+                                          int K, const double* scales, smdl_codes X_out) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    if (!sub || !scales) return h->fail(SMDL_E_ARG, "null pointer");
+    if (N < 0) return h->fail(SMDL_E_ARG, "N must be >= 0");
+    const int L = sub->L;
+    if (L < 1 || !sub->offsets || !sub->K_local) return h->fail(SMDL_E_ARG, "bad subsets");
+    if (sub->offsets[0] != 0 || sub->offsets[L] != N) return h->fail(SMDL_E_ARG, "offsets must run from 0 to N");
+    if (K < 1 || K > SMDL_MAX_K) return h->fail(SMDL_E_SHAPE, "K must be in [1, 1024]");
+    std::vector<int64_t> aoff(L + 1, 0);
+    for (int t = 0; t < L; ++t) {
+        if (sub->offsets[t + 1] < sub->offsets[t]) return h->fail(SMDL_E_ARG, "offsets must not decrease");
+        if (sub->K_local[t] < 1 || sub->K_local[t] > SMDL_MAX_K) return h->fail(SMDL_E_SHAPE, "K_local must be in [1, 1024]");
+        if (!(scales[t] >= 0.0)) return h->fail(SMDL_E_ARG, "scales must be >= 0");
+        aoff[t + 1] = aoff[t] + sub->K_local[t];
+    }
+    if (N == 0) return SMDL_OK;
+    if (!X1.idx || !X1.coef || !X1.nnz || !Z.idx || !Z.coef || !Z.nnz || !X_out.idx || !X_out.coef || !X_out.nnz)
+        return h->fail(SMDL_E_ARG, "null code array");
+    if (X1.s_max < 1 || Z.s_max < 1 || X1.s_max * Z.s_max > SMDL_MAX_COMPOSED)
+        return h->fail(SMDL_E_SHAPE, "X1.s_max * Z.s_max must be <= 64");
+    if (X_out.s_max < X1.s_max * Z.s_max || X_out.s_max > SMDL_MAX_COMPOSED)
+        return h->fail(SMDL_E_ARG, "X_out.s_max must be in [X1.s_max * Z.s_max, 64]");
+    (void)hipSetDevice(h->device);
+    int64_t* offs_dev = (int64_t*)h->ws("cc.offs", (size_t)(L + 1) * 8);
+    int64_t* aoff_dev = (int64_t*)h->ws("cc.aoff", (size_t)(L + 1) * 8);
+    double* sc_dev = (double*)h->ws("cc.scales", (size_t)L * 8);
+    int32_t* bad = (int32_t*)h->ws("cc.bad", 64);
+    if (!offs_dev || !aoff_dev || !sc_dev || !bad) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    smdl_status st;
+    if ((st = h->hip(launch_zero_i32(bad, 1, h->stream), "zero")) != SMDL_OK) return st;
+    if ((st = h->hip(hipMemcpyAsync(offs_dev, sub->offsets, (L + 1) * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK ||
+        (st = h->hip(hipMemcpyAsync(aoff_dev, aoff.data(), (L + 1) * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK ||
+        (st = h->hip(hipMemcpyAsync(sc_dev, scales, (size_t)L * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK)
+        return st;
+    if ((st = h->hip(launch_compose_codes(X1.idx, X1.coef, X1.nnz, X1.s_max, Z.idx, Z.coef, Z.nnz, Z.s_max, offs_dev,
+                                          aoff_dev, L, sc_dev, sub->perm, N, K, X_out.idx, X_out.coef, X_out.nnz,
+                                          X_out.s_max, bad, h->stream),
+                     "compose")) != SMDL_OK)
+        return st;
+    int32_t hbad = 0;
+    if ((st = h->hip(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, h->stream), "check")) != SMDL_OK) return st;
+    if ((st = h->hip(hipStreamSynchronize(h->stream), "compose")) != SMDL_OK) return st;
+    if (hbad) return h->fail(SMDL_E_ARG, "perm holds an index outside [0, N)");
+    return SMDL_OK;
 }
 
 // ------------------------------------------------------------------------------------------

@@ -17,6 +17,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int SMDL_MAX_M = 256;
 constexpr int SMDL_MAX_K = 1024;
 constexpr int SMDL_MAX_S = 16;
+constexpr int SMDL_MAX_COMPOSED = 64;   // atoms of a composed code (s_1 s_2)
 // LDS one gfx950 workgroup may use (static + dynamic), minus a margin for static variables.
 constexpr size_t SMDL_LDS_BYTES = 160 * 1024 - 256;
 
@@ -132,6 +133,13 @@ struct InitDesc {
 };
 hipError_t launch_code_scales(const float* coef, const int32_t* nnz, int s_stride,
                               const int64_t* offsets_dev, int L, double* scales, hipStream_t st);
+// Proposition 1 composition of Algorithm 1's codes (compose_codes_kernel); ls * ms <= 64,
+// ls * ms <= os <= 64; *bad is set when perm holds an entry outside [0, N).
+hipError_t launch_compose_codes(const int32_t* lidx, const float* lcoef, const int32_t* lnnz, int ls,
+                                const int32_t* midx, const float* mcoef, const int32_t* mnnz, int ms,
+                                const int64_t* offs_dev, const int64_t* aoff_dev, int L, const double* scales,
+                                const int64_t* perm, int64_t N, int K, int32_t* oidx, float* ocoef, int32_t* onnz,
+                                int os, int32_t* bad, hipStream_t st);
 hipError_t launch_pool_scale(const float* Dloc, const int64_t* atom_off_dev, int L, int m,
                              const double* scales, float* Ytil, int64_t total_atoms,
                              hipStream_t st);

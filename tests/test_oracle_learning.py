@@ -82,15 +82,21 @@ def test_proposition_1_on_composed_codes():
     E = Dt.T - D.T @ Z                                         # e_j as columns
     enorm = np.linalg.norm(E, axis=0)
     Yd = w.Y.astype(np.float64)
+    # r from the oracle's composition of the local codes over the unscaled D^(t) (x1 * c_t)
+    loc = [oracle.omp(Dt[40 * t:40 * (t + 1)], Yd[w.perm[offs[t]:offs[t + 1]]], s1) for t in range(2)]
+    X1u = oracle.Codes(np.vstack([c.idx for c in loc]),
+                       np.vstack([loc[t].coef * sc[t] for t in range(2)]),
+                       np.concatenate([c.nnz for c in loc]))
+    R = oracle.compose_codes(X1u, offs, [40, 40], Zc, sc, 48, perm=w.perm)
     for t in range(2):
         sub = Yd[w.perm[offs[t]:offs[t + 1]]]
-        c1 = oracle.omp(Dt[40 * t:40 * (t + 1)], sub, s1)      # x1 against D~ (block t)
+        c1 = loc[t]                                            # x1 against D~ (block t)
         X1 = np.zeros((len(sub), 80))
         X1[:, 40 * t:40 * (t + 1)] = c1.dense(40)
         for n in range(len(sub)):
             x1 = X1[n]
             e1 = sub[n] - Dt.T @ x1
-            r = Z @ x1
+            r = R[w.perm[offs[t] + n]]
             np.testing.assert_allclose(sub[n], D.T @ r + E @ x1 + e1, rtol=0, atol=1e-10)
             assert np.count_nonzero(np.abs(r) > 0) <= s1 * s2
             used = np.nonzero(x1)[0]
