@@ -123,6 +123,12 @@ smdl_status smdl_mod_update(smdl_t h, const float* Y, int m, int64_t N, smdl_cod
 smdl_status smdl_learn(smdl_t h, const float* Y, int m, int64_t N, int K, int s, int iters,
                        float* D_out, smdl_codes X_out);
 
+/* The same alternation started from a given dictionary D_init (device m x K, unit-normalised
+ * before the first coding; it may be D_out itself) instead of the first K signals (for example
+ * the overcomplete DCT of Section 3.2.1).  N >= 1. */
+smdl_status smdl_learn_init(smdl_t h, const float* Y, int m, int64_t N, int K, int s, int iters,
+                            const float* D_init, float* D_out, smdl_codes X_out);
+
 /* Subsets of Algorithm 1, step 1.  Subset t is the signals perm[offsets[t] .. offsets[t+1]). */
 typedef struct {
     int L;                       /* number of subsets, >= 1                                  */
@@ -144,6 +150,11 @@ typedef struct {
     int s_merge;       /* sparsity of the merge (step 3, s2)                                  */
     int s_final;       /* sparsity of the final coding of all N signals                       */
     uint32_t flags;    /* SMDL_PER_SUBSET_LAUNCH | SMDL_NO_GRAPH | SMDL_COMPOSE_CODES          */
+    const float* D_local_init;  /* device m x max_t K_local[t], or NULL: subset t starts from the
+                                   first K_local[t] columns of this matrix (unit-normalised) instead
+                                   of its first K_local[t] signals                               */
+    const float* D_merge_init;  /* device m x K, or NULL: the merge starts from this dictionary
+                                   (unit-normalised) instead of the first K pooled columns       */
 } smdl_learn_opts;
 
 /*
@@ -185,6 +196,17 @@ smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, int64_t N,
  */
 smdl_status smdl_compose_codes(smdl_t h, int64_t N, const smdl_subsets* sub, smdl_codes X1, smdl_codes Z,
                                int K, const double* scales, smdl_codes X_out);
+
+/*
+ * Image denoising (Section 3.2.2).  Every p x p patch of the H x W image (row-major, device;
+ * stride 1 in both directions: (H - p + 1)(W - p + 1) patches, patch pixel (r, c) at index
+ * r p + c) is coded by the error-constrained OMP ||y - D x||_2 <= eps (eps > 0, at most s_max
+ * atoms) against D (device, m x K column-major, m = p * p <= 256); out (device H x W) receives
+ * the mean of the overlapping patch estimates D x at every pixel.  The paper takes
+ * eps = 8.5 sigma for noise of standard deviation sigma.
+ */
+smdl_status smdl_denoise(smdl_t h, const float* img, int H, int W, int p, const float* D, int K, float eps,
+                         int s_max, float* out);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Learned support proposer                                                                 */

@@ -289,6 +289,30 @@ def compose_codes(X1: Codes, offsets, K_local, Z: Codes, scales, K: int, perm=No
     return R
 
 
+def denoise(img, D, p: int, eps: float, s_max: int):
+    """Section 3.2.2 written out: every p x p patch of the image (stride 1 in both directions) is
+    coded by the error-constrained OMP (||y - D x||_2 <= eps) against D, and every pixel of the
+    output is the mean of the estimates D x of the patches that cover it.  FP64 throughout.
+    Returns (image, codes of the patches in row-major patch order)."""
+    img = np.asarray(img, np.float64)
+    D = _d(D)
+    H, W = img.shape
+    PH, PW = H - p + 1, W - p + 1
+    patches = np.empty((PH * PW, p * p))
+    for pi in range(PH):
+        for pj in range(PW):
+            patches[pi * PW + pj] = img[pi:pi + p, pj:pj + p].ravel()
+    codes = omp(D, patches, s_max, eps)
+    est = codes.dense(D.shape[0]) @ D
+    acc = np.zeros((H, W))
+    cnt = np.zeros((H, W))
+    for pi in range(PH):
+        for pj in range(PW):
+            acc[pi:pi + p, pj:pj + p] += est[pi * PW + pj].reshape(p, p)
+            cnt[pi:pi + p, pj:pj + p] += 1.0
+    return acc / cnt, codes
+
+
 def tie_mask(codes: Codes, eps: float = 0.0, margin: float = 1e-5, tau: float = TAU,
              dep_tol: float = DEP_TOL) -> np.ndarray:
     """Signals whose FP64 trace comes close to a decision boundary (excluded from

@@ -48,7 +48,8 @@ class _Subsets(C.Structure):
 
 class _LearnOpts(C.Structure):
     _fields_ = [("iters_local", C.c_int), ("iters_merge", C.c_int), ("s_merge", C.c_int),
-                ("s_final", C.c_int), ("flags", C.c_uint32)]
+                ("s_final", C.c_int), ("flags", C.c_uint32), ("D_local_init", C.c_void_p),
+                ("D_merge_init", C.c_void_p)]
 
 
 class _TrainOpts(C.Structure):
@@ -70,9 +71,11 @@ def _load():
         "smdl_omp_code": [vp, vp, i32, i32, vp, i64, i32, f32, _Codes, vp],
         "smdl_mod_update": [vp, vp, i32, i64, _Codes, i32, vp, C.POINTER(C.c_int32)],
         "smdl_learn": [vp, vp, i32, i64, i32, i32, i32, vp, _Codes],
+        "smdl_learn_init": [vp, vp, i32, i64, i32, i32, i32, vp, vp, _Codes],
         "smdl_split_merge_learn": [vp, vp, i32, i64, C.POINTER(_Subsets), i32, C.POINTER(_LearnOpts), vp,
                                    _Codes, vp, C.POINTER(C.c_double)],
         "smdl_compose_codes": [vp, i64, C.POINTER(_Subsets), _Codes, _Codes, i32, C.POINTER(C.c_double), _Codes],
+        "smdl_denoise": [vp, vp, i32, i32, i32, vp, i32, f32, i32, vp],
         "smdl_prop_create": [vp, i32, C.POINTER(C.c_int), C.POINTER(C.POINTER(C.c_float)),
                              C.POINTER(C.POINTER(C.c_float)), C.POINTER(vp)],
         "smdl_prop_destroy": [vp],
@@ -221,19 +224,27 @@ class Handle:
         return nu.value
 
     # ---- learning -------------------------------------------------------------------
-    def learn(self, Y: torch.Tensor, K: int, s: int, iters: int, codes: bool = True):
+    def learn(self, Y: torch.Tensor, K: int, s: int, iters: int, codes: bool = True,
+              D_init: torch.Tensor | None = None):
+        """The standard alternation; from the first K signals, or from D_init (K, m) when given."""
         _dev_tensor(Y, torch.float32, "Y")
         N, m = Y.shape
         D = torch.empty((K, m), dtype=torch.float32, device=Y.device)
         X = Codes.empty(N, s, Y.device) if codes else None
         xc = X._c() if X is not None else _Codes(None, None, None, s)
-        self._check(lib().smdl_learn(self._h, _ptr(Y), m, N, K, s, iters, _ptr(D), xc))
+        if D_init is None:
+            self._check(lib().smdl_learn(self._h, _ptr(Y), m, N, K, s, iters, _ptr(D), xc))
+        else:
+            _dev_tensor(D_init, torch.float32, "D_init", (K, m))
+            self._check(lib().smdl_learn_init(self._h, _ptr(Y), m, N, K, s, iters, _ptr(D_init), _ptr(D), xc))
         return D, X
 
     def split_merge_learn(self, Y: torch.Tensor, perm: torch.Tensor | None, offsets, K_local, s_local,
                           K: int, iters_local: int, iters_merge: int, s_merge: int, s_final: int,
-                          flags: int = 0, codes: bool = True, local: bool = False):
-        """Algorithm 1.  Returns (D, codes or None, D_local or None, scales (np.float64[L]))."""
+                          flags: int = 0, codes: bool = True, local: bool = False,
+                          D_local_init: torch.Tensor | None = None, D_merge_init: torch.Tensor | None = None):
+        """Algorithm 1.  Returns (D, codes or None, D_local or None, scales (np.float64[L])).
+        D_local_init (max K_local, m) and D_merge_init (K, m) replace the first-columns starts."""
         _dev_tensor(Y, torch.float32, "Y")
         N, m = Y.shape
         offsets = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -246,7 +257,13 @@ class Handle:
                        offsets.ctypes.data_as(C.POINTER(C.c_int64)),
                        K_local.ctypes.data_as(C.POINTER(C.c_int32)),
                        s_local.ctypes.data_as(C.POINTER(C.c_int32)))
-        opts = _LearnOpts(iters_local, iters_merge, s_merge, s_final, flags)
+        if D_local_init is not None:
+            _dev_tensor(D_local_init, torch.float32, "D_local_init", (int(K_local.max()), m))
+        if D_merge_init is not None:
+            _dev_tensor(D_merge_init, torch.float32, "D_merge_init", (K, m))
+        opts = _LearnOpts(iters_local, iters_merge, s_merge, s_final, flags,
+                          _ptr(D_local_init).value if D_local_init is not None else None,
+                          _ptr(D_merge_init).value if D_merge_init is not None else None)
         D = torch.empty((K, m), dtype=torch.float32, device=Y.device)
         s_out = int(s_local.max()) * s_merge if flags & SMDL_COMPOSE_CODES else s_final
         X = Codes.empty(N, s_out, Y.device) if codes else None
@@ -275,6 +292,16 @@ class Handle:
         self._check(lib().smdl_compose_codes(self._h, N, C.byref(sub), X1._c(), Z._c(), K,
                                              scales.ctypes.data_as(C.POINTER(C.c_double)), X._c()))
         return X
+
+    def denoise(self, img: torch.Tensor, D: torch.Tensor, p: int, eps: float, s_max: int) -> torch.Tensor:
+        """Section 3.2.2: error-constrained OMP of every p x p patch, overlapping estimates averaged."""
+        _dev_tensor(img, torch.float32, "img")
+        H, W = img.shape
+        K = D.shape[0]
+        _dev_tensor(D, torch.float32, "D", (K, p * p))
+        out = torch.empty_like(img)
+        self._check(lib().smdl_denoise(self._h, _ptr(img), H, W, p, _ptr(D), K, float(eps), s_max, _ptr(out)))
+        return out
 
     def phase_ms(self):
         v = (C.c_float * 3)()

@@ -545,7 +545,7 @@ smdl_status learn_sets(smdl_t h, int m, std::vector<SetSpec>& sets, int iters, c
         std::vector<InitDesc> idd(sets.size());
         int maxK = 0;
         for (size_t i = 0; i < sets.size(); ++i) {
-            idd[i] = InitDesc{sets[i].Y, const_cast<float*>(sets[i].D), sets[i].K, 0};
+            idd[i] = InitDesc{sets[i].init ? sets[i].init : sets[i].Y, const_cast<float*>(sets[i].D), sets[i].K, 0};
             maxK = std::max(maxK, sets[i].K);
         }
         void* dd = h->ws((t + ".init").c_str(), idd.size() * sizeof(InitDesc));
@@ -642,14 +642,15 @@ smdl_status learn_sets(smdl_t h, int m, std::vector<SetSpec>& sets, int iters, c
     return h->hip(hipStreamSynchronize(h->stream), "learn");
 }
 
-extern "C" smdl_status smdl_learn(smdl_t h, const float* Y, int m, int64_t N, int K, int s, int iters,
-                                  float* D_out, smdl_codes X_out) {
+static smdl_status learn_impl(smdl_t h, const float* Y, int m, int64_t N, int K, int s, int iters,
+                              const float* D_init, float* D_out, smdl_codes X_out) {
     if (!h) return SMDL_E_ARG;
     h->err.clear();
     smdl_status st = check_dims(h, m, K, s);
     if (st != SMDL_OK) return st;
     if (iters < 0) return h->fail(SMDL_E_ARG, "iters must be >= 0");
-    if (N < K) return h->fail(SMDL_E_ARG, "need at least K signals (initialisation uses the first K)");
+    if (!D_init && N < K) return h->fail(SMDL_E_ARG, "need at least K signals (initialisation uses the first K)");
+    if (N < 1) return h->fail(SMDL_E_ARG, "N must be >= 1");
     if (!Y || !D_out) return h->fail(SMDL_E_ARG, "null pointer");
     if (X_out.idx && (st = check_codes(h, X_out, N, s)) != SMDL_OK) return st;
     if (N * 16 > INT32_MAX) return h->fail(SMDL_E_SHAPE, "N too large for one data set");
@@ -667,12 +668,24 @@ extern "C" smdl_status smdl_learn(smdl_t h, const float* Y, int m, int64_t N, in
     }
     std::vector<SetSpec> sets(1);
     sets[0].Y = Y;
+    sets[0].init = D_init;
     sets[0].n = N;
     sets[0].K = K;
     sets[0].s = s;
     sets[0].D = D_out;
     sets[0].out0 = 0;
     return learn_sets(h, m, sets, iters, out, X_out.idx != nullptr, 0, "learn");
+}
+
+extern "C" smdl_status smdl_learn(smdl_t h, const float* Y, int m, int64_t N, int K, int s, int iters,
+                                  float* D_out, smdl_codes X_out) {
+    return learn_impl(h, Y, m, N, K, s, iters, nullptr, D_out, X_out);
+}
+
+extern "C" smdl_status smdl_learn_init(smdl_t h, const float* Y, int m, int64_t N, int K, int s, int iters,
+                                       const float* D_init, float* D_out, smdl_codes X_out) {
+    if (h && !D_init) return h->fail(SMDL_E_ARG, "null initial dictionary");
+    return learn_impl(h, Y, m, N, K, s, iters, D_init, D_out, X_out);
 }
 
 extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, int64_t N,
@@ -694,7 +707,8 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
     for (int t = 0; t < L; ++t) {
         const int64_t n = sub->offsets[t + 1] - sub->offsets[t];
         if ((st = check_dims(h, m, sub->K_local[t], sub->s_local[t])) != SMDL_OK) return st;
-        if (n < sub->K_local[t]) return h->fail(SMDL_E_ARG, "every subset needs at least K_local signals");
+        if (!o->D_local_init && n < sub->K_local[t]) return h->fail(SMDL_E_ARG, "every subset needs at least K_local signals");
+        if (n < 1) return h->fail(SMDL_E_ARG, "every subset needs at least one signal");
         if (n * 16 > INT32_MAX) return h->fail(SMDL_E_SHAPE, "subset too large");
         sumK += sub->K_local[t];
         s_loc_max = std::max(s_loc_max, (int)sub->s_local[t]);
@@ -751,6 +765,7 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
     std::vector<SetSpec> sets(L);
     for (int t = 0; t < L; ++t) {
         sets[t].Y = Yp + sub->offsets[t] * m;
+        sets[t].init = o->D_local_init;
         sets[t].n = sub->offsets[t + 1] - sub->offsets[t];
         sets[t].K = sub->K_local[t];
         sets[t].s = sub->s_local[t];
@@ -775,6 +790,7 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
     if (!mc.idx || !mc.coef || !mc.nnz) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     std::vector<SetSpec> ms(1);
     ms[0].Y = Ytil;
+    ms[0].init = o->D_merge_init;
     ms[0].n = sumK;
     ms[0].K = K;
     ms[0].s = o->s_merge;

@@ -42,6 +42,7 @@ struct smdl_ctx {
 
 struct SetSpec {
     const float* Y = nullptr;   // signals of the set (m each)
+    const float* init = nullptr;  // initial dictionary (m x K), NULL: the first K signals
     int64_t n = 0;
     int K = 0, s = 1;
     const float* D = nullptr;   // m x K (written by learning, read by coding)

@@ -39,3 +39,9 @@ def atom_recovery(D_true, D_hat, thr: float = 0.98) -> float:
     nb = np.linalg.norm(B, axis=1, keepdims=True)
     B = B / np.where(nb > 0, nb, 1.0)
     return float(np.mean(np.abs(A @ B.T).max(axis=1) >= thr))
+
+
+def psnr(clean, est, peak: float = 255.0) -> float:
+    """Peak signal-to-noise ratio of an image estimate, 20 log10(peak / RMSE) in dB (Section 3.2)."""
+    d = np.asarray(clean, np.float64) - np.asarray(est, np.float64)
+    return float(20.0 * np.log10(peak / np.sqrt(np.mean(d * d))))

@@ -201,6 +201,53 @@ def synthetic_e1(trial: int, iters: int = 100, N: int = 40000) -> Workload:
                          iters_local=iters, iters_merge=iters, s_merge=2, s_final=6)
 
 
+def odct(p: int, kh: int, kw: int) -> np.ndarray:
+    """Overcomplete two-dimensional DCT for p x p patches (the initial dictionary of Section
+    3.2.1): the Kronecker product of two one-dimensional overcomplete cosine sets of kh and kw
+    atoms of length p (atom k: cos(pi n k / k_total), n = 0 .. p-1; the mean removed from every
+    atom but the first; unit length).  Shape (kh * kw, p * p), float64; atom u kw + v has pixel
+    (r, c) at index r p + c equal to C_kh[r, u] C_kw[c, v]."""
+    def one(k):
+        C = np.cos(np.outer(np.arange(p), np.arange(k)) * np.pi / k)
+        C[:, 1:] -= C[:, 1:].mean(axis=0)
+        return C / np.linalg.norm(C, axis=0)
+    return np.kron(one(kh), one(kw)).T.copy()
+
+
+def synthetic_image(rng: np.random.Generator, H: int = 256, W: int = 256) -> np.ndarray:
+    """A seeded piecewise-smooth grey-level image in [0, 255] (a stand-in for the natural images
+    of Section 3.2, which are not available): a smooth background of a few low-frequency cosines,
+    ellipses and rectangles of constant offsets (sharp edges) and one striped texture patch."""
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    img = np.full((H, W), 110.0)
+    for _ in range(4):
+        fy, fx = rng.uniform(0.2, 2.0, 2) * np.pi / np.array([H, W])
+        img += rng.uniform(10, 30) * np.cos(fy * y + fx * x + rng.uniform(0, 2 * np.pi))
+    for _ in range(8):
+        cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+        ry, rx = rng.uniform(H / 16, H / 4), rng.uniform(W / 16, W / 4)
+        img[((y - cy) / ry) ** 2 + ((x - cx) / rx) ** 2 <= 1.0] += rng.uniform(-60, 60)
+    for _ in range(6):
+        y0, x0 = rng.integers(0, H - 8), rng.integers(0, W - 8)
+        y1, x1 = y0 + rng.integers(8, H // 3), x0 + rng.integers(8, W // 3)
+        img[y0:y1, x0:x1] += rng.uniform(-50, 50)
+    y0, x0 = rng.integers(0, H // 2), rng.integers(0, W // 2)
+    per = rng.uniform(4, 12)
+    img[y0:y0 + H // 4, x0:x0 + W // 4] += 25 * np.sign(np.sin(2 * np.pi * x[y0:y0 + H // 4, x0:x0 + W // 4] / per))
+    return np.clip(img, 0.0, 255.0)
+
+
+def image_patches(rng: np.random.Generator, images, n: int, p: int) -> np.ndarray:
+    """n random p x p patches (rows, pixel (r, c) at r p + c) of the given images, float32."""
+    out = np.empty((n, p * p), dtype=np.float32)
+    which = rng.integers(0, len(images), n)
+    for i in range(n):
+        im = images[which[i]]
+        r, c = rng.integers(0, im.shape[0] - p + 1), rng.integers(0, im.shape[1] - p + 1)
+        out[i] = im[r:r + p, c:c + p].ravel()
+    return out
+
+
 def fresh_signals(w: Workload, stream: int, N: int, s0: int, sigma: float) -> np.ndarray:
     """Fresh signals from the same generating dictionary as workload ``w``
     (training pairs use STREAM_TRAIN, evaluation signals STREAM_EVAL)."""
