@@ -370,15 +370,20 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ Y, 
 }
 
 // ---------------------------------------------------------------------------------------------
-// The whole network on R batch rows per work group (see RowsArgs).  512 threads = 8 waves.  The
+// The whole network on R batch rows per work group (see RowsArgs), 8 or 16 waves.  The
 // output of a layer is cut into 32-column tiles that the waves take in turn; a tile is R x 32 =
 // (R / 16) x 2 blocks of 16 x 16 on v_mfma_f32_16x16x32_bf16.  A fragments come from the BF16
 // activations in LDS, B fragments (weight rows, L2 resident) from global memory, the loads of
 // the next four k-steps issued before the current four are multiplied.  Every activation of the
 // R rows stays in LDS until the backward pass has used it as a ReLU mask; each delta overwrites
 // the activation that masked it.
-constexpr int FT = 512;        // threads of the fused network kernel
 constexpr int ACT_PAD = 8;     // BF16 padding per LDS activation row (16 bytes: rows 4 banks apart)
+
+// Threads of the fused network kernel: 16 waves for 16 rows (a training batch spreads over few
+// work groups, so each takes more independent tile chains; 108 VGPRs with one register set of
+// fragments in flight per wave), 8 waves for 32 rows (two register sets in flight per wave).
+template <int R>
+constexpr int rows_threads() { return R == 16 ? 1024 : 512; }
 
 // B fragments (fragment-ordered weight row blocks n0 / 16 and n0 / 16 + 1) of k-steps s .. s + 3
 // (clamped; a step past the end is loaded but not used).
@@ -416,11 +421,12 @@ __device__ __forceinline__ void rows_mma4(f32x4 (&acc)[RB][2], const bf16x8 (&b)
 }
 
 // acc = rows 0 .. R - 1 of A (LDS, ld lda) times weight rows n0 .. n0 + 31 of Bw (fragment order)
-// over K.  The B fragments go through two register sets in turn: the loads of the next four
-// k-steps are in flight while the current four are multiplied.  Every iteration issues both
-// sets' loads unconditionally (clamped to the last step), so that no set is overwritten or read
-// while loads of another path may still be pending into it.
-template <int RB>
+// over K.  With DB the B fragments go through two register sets in turn: the loads of the next
+// four k-steps are in flight while the current four are multiplied; every iteration then issues
+// both sets' loads unconditionally (clamped to the last step), so that no set is overwritten or
+// read while loads of another path may still be pending into it.  Without DB one set serves:
+// four k-steps are loaded, then multiplied.
+template <int RB, bool DB>
 __device__ __forceinline__ void rows_tile(const uint16_t* __restrict__ A, int lda, const uint16_t* __restrict__ Bw,
                                           int K, int n0, int lane, f32x4 (&acc)[RB][2]) {
     const int r16 = lane & 15, kq = lane >> 4;
@@ -433,13 +439,21 @@ __device__ __forceinline__ void rows_tile(const uint16_t* __restrict__ A, int ld
         acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     const int nsteps = K >> 5;
-    bf16x8 b0[4][2], b1[4][2];
-    rows_load_b(b0, bp0, bp1, 0, nsteps);
-    for (int s0 = 0; s0 < nsteps; s0 += 8) {
-        rows_load_b(b1, bp0, bp1, s0 + 4, nsteps);
-        rows_mma4<RB>(acc, b0, ap, lda, s0, nsteps);
-        rows_load_b(b0, bp0, bp1, s0 + 8, nsteps);
-        rows_mma4<RB>(acc, b1, ap, lda, s0 + 4, nsteps);
+    if (DB) {
+        bf16x8 b0[4][2], b1[4][2];
+        rows_load_b(b0, bp0, bp1, 0, nsteps);
+        for (int s0 = 0; s0 < nsteps; s0 += 8) {
+            rows_load_b(b1, bp0, bp1, s0 + 4, nsteps);
+            rows_mma4<RB>(acc, b0, ap, lda, s0, nsteps);
+            rows_load_b(b0, bp0, bp1, s0 + 8, nsteps);
+            rows_mma4<RB>(acc, b1, ap, lda, s0 + 4, nsteps);
+        }
+    } else {
+        bf16x8 b0[4][2];
+        for (int s0 = 0; s0 < nsteps; s0 += 4) {
+            rows_load_b(b0, bp0, bp1, s0, nsteps);
+            rows_mma4<RB>(acc, b0, ap, lda, s0, nsteps);
+        }
     }
 }
 
@@ -473,8 +487,10 @@ __device__ __forceinline__ void store_deltas(const float (&v)[RB][2][4], uint16_
 }
 
 template <int R>
-__global__ __launch_bounds__(FT) void mlp_rows_kernel(RowsArgs g) {
+__global__ __launch_bounds__(rows_threads<R>()) void mlp_rows_kernel(RowsArgs g) {
     constexpr int RB = R / 16;
+    constexpr int FT = rows_threads<R>();
+    constexpr bool DB = FT == 512;
     extern __shared__ __align__(16) uint16_t act[];
     __shared__ int32_t s_src[R];
     __shared__ double s_loss[FT / 64];
@@ -497,7 +513,7 @@ __global__ __launch_bounds__(FT) void mlp_rows_kernel(RowsArgs g) {
     }
     __syncthreads();
     {
-        constexpr int TPR = FT / R;                  // threads per row (16 or 32), lanes of one wave
+        constexpr int TPR = FT / R;                  // threads per row (16 or 64), lanes of one wave
         constexpr int NCH = SMDL_MAX_M / 4 / TPR;    // float4 chunks per thread at most
         const int rr = tid / TPR, pt = tid % TPR;
         const int src = s_src[rr];
@@ -554,7 +570,7 @@ __global__ __launch_bounds__(FT) void mlp_rows_kernel(RowsArgs g) {
             const int n0 = 32 * ct;
             const float bj[2] = {g.bias[l][n0 + r16], g.bias[l][n0 + 16 + r16]};
             f32x4 acc[RB][2];
-            rows_tile<RB>(A, lda, g.W[l], wi, n0, lane, acc);
+            rows_tile<RB, DB>(A, lda, g.W[l], wi, n0, lane, acc);
             if (!last) {
                 // ReLU; BF16 into LDS (next layer's input) and transposed into hT[l + 1]
 #pragma unroll
@@ -624,7 +640,7 @@ __global__ __launch_bounds__(FT) void mlp_rows_kernel(RowsArgs g) {
         for (int ct = wave; ct < wi / 32; ct += FT / 64) {
             const int n0 = 32 * ct;
             f32x4 acc[RB][2];
-            rows_tile<RB>(A, lda, g.WT[l], wo, n0, lane, acc);
+            rows_tile<RB, DB>(A, lda, g.WT[l], wo, n0, lane, acc);
             float v[RB][2][4];
 #pragma unroll
             for (int i = 0; i < RB; ++i)
@@ -731,9 +747,9 @@ hipError_t launch_mlp_rows(const RowsArgs& a, int R, hipStream_t st) {
         attr_set = true;
     }
     if (R == 32)
-        hipLaunchKernelGGL(mlp_rows_kernel<32>, dim3((unsigned)(a.Bpad / 32)), dim3(FT), lds, st, a);
+        hipLaunchKernelGGL(mlp_rows_kernel<32>, dim3((unsigned)(a.Bpad / 32)), dim3(rows_threads<32>()), lds, st, a);
     else
-        hipLaunchKernelGGL(mlp_rows_kernel<16>, dim3((unsigned)(a.Bpad / 16)), dim3(FT), lds, st, a);
+        hipLaunchKernelGGL(mlp_rows_kernel<16>, dim3((unsigned)(a.Bpad / 16)), dim3(rows_threads<16>()), lds, st, a);
     return hipGetLastError();
 }
 
