@@ -44,11 +44,11 @@ __device__ __forceinline__ const uint16_t* pk_frag(const uint16_t* base, int nb,
     return base + (((int64_t)nb * (K >> 5)) * 64 + lane) * 8;
 }
 
-// Partial 32 x 32 tile (m0, n0) of A B^T over the k-steps (32 wide) wave, wave + 4, ...:
+// Partial 32 x 32 tile (m0, n0) of A B^T over the k-steps (32 wide) wave, wave + NW, ...:
 // 2 x 2 blocks of 16 x 16; the loads of up to four k-steps are issued before their MFMAs.
 // A is row-major (ld lda; rows >= M read clamped, their results discarded) or, with A_PK, in
 // fragment order; B is in fragment order (N % 32 == 0).
-template <bool A_PK>
+template <bool A_PK, int NW>
 __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int lda, int M,
                                            const uint16_t* __restrict__ B, int K,
                                            int m0, int n0, int wave, int lane, f32x4 (&acc)[2][2]) {
@@ -73,11 +73,11 @@ __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int l
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int nsteps = K / 32;
-    for (int s0 = wave; s0 < nsteps; s0 += 16) {
+    for (int s0 = wave; s0 < nsteps; s0 += 4 * NW) {
         bf16x8 a[4][2], b[4][2];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int st = min(s0 + 4 * c, nsteps - 1);
+            const int st = min(s0 + NW * c, nsteps - 1);
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
                 a[c][f] = *reinterpret_cast<const bf16x8*>(ap[f] + (int64_t)astep * st);
@@ -86,7 +86,7 @@ __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int l
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            if (s0 + 4 * c >= nsteps) break;
+            if (s0 + NW * c >= nsteps) break;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -96,14 +96,15 @@ __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int l
     }
 }
 
-// The full 32 x 32 tile: the four waves' partials summed through LDS into tile[r][c].
-template <bool A_PK>
+// The full 32 x 32 tile: the NW waves' partials summed through LDS into tile[r][c] (the first
+// 256 threads form the sums).
+template <bool A_PK, int NW>
 __device__ __forceinline__ void nt_tile(const uint16_t* __restrict__ A, int lda, int M,
                                         const uint16_t* __restrict__ B, int K,
                                         int m0, int n0, float (*part)[TILE][RP], float (*tile)[RP]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     f32x4 acc[2][2];
-    nt_partial<A_PK>(A, lda, M, B, K, m0, n0, wave, lane, acc);
+    nt_partial<A_PK, NW>(A, lda, M, B, K, m0, n0, wave, lane, acc);
     // D[i][j] of a 16 x 16 block sits in lane j + 16 (i / 4), register i % 4
     const int r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -113,10 +114,16 @@ __device__ __forceinline__ void nt_tile(const uint16_t* __restrict__ A, int lda,
 #pragma unroll
             for (int q = 0; q < 4; ++q) part[wave][16 * i + 4 * kq + q][16 * j + r16] = acc[i][j][q];
     __syncthreads();
-    const int r = tid >> 3, c0 = (tid & 7) * 4;
+    if (tid < 256) {
+        const int r = tid >> 3, c0 = (tid & 7) * 4;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-        tile[r][c0 + e] = (part[0][r][c0 + e] + part[1][r][c0 + e]) + (part[2][r][c0 + e] + part[3][r][c0 + e]);
+        for (int e = 0; e < 4; ++e) {
+            float v = (part[0][r][c0 + e] + part[1][r][c0 + e]) + (part[2][r][c0 + e] + part[3][r][c0 + e]);
+            if (NW == 8)
+                v += (part[4][r][c0 + e] + part[5][r][c0 + e]) + (part[6][r][c0 + e] + part[7][r][c0 + e]);
+            tile[r][c0 + e] = v;
+        }
+    }
     __syncthreads();
 }
 
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
         const int src = g.rows ? g.rows[row] : row;
         tbits = g.tmask[(int64_t)src * g.tstride + ((n0 + cl0) >> 5)] >> ((n0 + cl0) & 31);
     }
-    nt_tile<false>(g.A, g.lda, g.M, g.B, g.K, m0, n0, part, tile);
+    nt_tile<false, 4>(g.A, g.lda, g.M, g.B, g.K, m0, n0, part, tile);
 
     double lsum = 0.0;
     float v[4];
@@ -217,12 +224,16 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
     }
 }
 
+
 // Weight gradients of every layer in one launch: blocks [tile0_l, tile0_l + tiles_l) form
 // 32 x 32 tiles of dW_l = d_l^T h_{l-1}; the blocks after them form the bias gradients from
 // the column sums, 64 columns each.  With adam set, the gradient is applied at once (Adam on the FP32 master,
 // BF16 copies W and W^T written); otherwise dW and db are stored.
-__global__ __launch_bounds__(256) void wgrad_kernel(WgArgs g) {
-    __shared__ float part[4][TILE][RP];
+// NW waves split the reduction over the batch of a 32 x 32 tile: 8 when the tiles are few (a
+// small network), 4 when they already fill the chip.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void wgrad_kernel(WgArgs g) {
+    __shared__ float part[NW][TILE][RP];
     __shared__ float tile[TILE][RP];
     __shared__ uint16_t tT[TILE][TILE + 2];
     const int tid = threadIdx.x;
@@ -234,22 +245,25 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs g) {
         c2 = 1.f - powf(g.b2, t);
     }
     if (blk >= g.bias_block0) {
-        // bias gradients, 64 columns per block: thread (c, p) sums the parts p, p + 4, ...
+        // bias gradients, 64 columns per block: thread (c, p) sums the parts p, p + 8, ...
         int l = 0, bb = blk - g.bias_block0;
         while (bb >= (g.L[l].wo + 63) / 64) bb -= (g.L[l++].wo + 63) / 64;
         const WgLayer& L = g.L[l];
+        constexpr int NP = NW;
         const int c = tid & 63, p0 = tid >> 6;
         const int o = 64 * bb + c;
         float s = 0.f;
         if (o < L.wo) {
-#pragma unroll 8
-            for (int r = p0; r < L.nparts; r += 4) s += L.colpart[(int64_t)r * L.wo + o];
+#pragma unroll 4
+            for (int r = p0; r < L.nparts; r += NP) s += L.colpart[(int64_t)r * L.wo + o];
         }
-        float* red = &part[0][0][0];             // 4 x 64 floats
+        float* red = &part[0][0][0];             // NP x 64 floats
         red[p0 * 64 + c] = s;
         __syncthreads();
         if (tid < 64 && o < L.wo) {
-            s = (red[c] + red[64 + c]) + (red[128 + c] + red[192 + c]);
+            s = 0.f;
+#pragma unroll
+            for (int q = 0; q < NP; q += 2) s += red[q * 64 + c] + red[(q + 1) * 64 + c];
             if (g.adam) {
                 const float a = g.b1 * L.mb[o] + (1.f - g.b1) * s;
                 const float b = g.b2 * L.vb[o] + (1.f - g.b2) * s * s;
@@ -267,11 +281,19 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs g) {
     const WgLayer& L = g.L[l];
     const int t = blk - L.tile0;
     const int m0 = (t / L.ntn) * TILE, n0 = (t % L.ntn) * TILE;    // rows o, columns i
-    nt_tile<true>(L.dT, 0, L.wo, L.hT, g.Bpad, m0, n0, part, tile);
-    const int ol = tid >> 3, il0 = (tid & 7) * 4;
+    // the Adam state of the thread's four entries is requested before the product
+    const bool ep = tid < 256;
+    const int ol = (tid & 255) >> 3, il0 = (tid & 7) * 4;
     const int o = m0 + ol, i0 = n0 + il0;
-    const bool ok = o < L.wo && i0 < L.wi;       // wi % 4 == 0
+    const bool ok = ep && o < L.wo && i0 < L.wi;
     const int64_t idx = (int64_t)o * L.wi + i0;
+    float4 m4 = make_float4(0.f, 0.f, 0.f, 0.f), v4 = m4, w4 = m4;
+    if (g.adam && ok) {
+        m4 = *reinterpret_cast<const float4*>(L.mW + idx);
+        v4 = *reinterpret_cast<const float4*>(L.vW + idx);
+        w4 = *reinterpret_cast<const float4*>(L.W + idx);
+    }
+    nt_tile<true, NW>(L.dT, 0, L.wo, L.hT, g.Bpad, m0, n0, part, tile);
     if (!g.adam) {
         if (ok)
             *reinterpret_cast<float4*>(L.dW_out + idx) =
@@ -279,9 +301,6 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs g) {
         return;
     }
     if (ok) {
-        const float4 m4 = *reinterpret_cast<const float4*>(L.mW + idx);
-        const float4 v4 = *reinterpret_cast<const float4*>(L.vW + idx);
-        const float4 w4 = *reinterpret_cast<const float4*>(L.W + idx);
         float mm[4] = {m4.x, m4.y, m4.z, m4.w}, vv[4] = {v4.x, v4.y, v4.z, v4.w}, ww[4] = {w4.x, w4.y, w4.z, w4.w};
         uint16_t hb[4];
 #pragma unroll
@@ -301,8 +320,8 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgArgs g) {
     }
     __syncthreads();
     // W^T: thread t writes row i = t / 8, entries o = 4 (t % 8) .. + 3
-    const int ic = tid >> 3, o0 = (tid & 7) * 4;
-    if (n0 + ic < L.wi && m0 + o0 < L.wo) {
+    const int ic = (tid & 255) >> 3, o0 = (tid & 7) * 4;
+    if (ep && n0 + ic < L.wi && m0 + o0 < L.wo) {
         const uint32_t lo = (uint32_t)tT[ic][o0] | ((uint32_t)tT[ic][o0 + 1] << 16);
         const uint32_t hi = (uint32_t)tT[ic][o0 + 2] | ((uint32_t)tT[ic][o0 + 3] << 16);
         *reinterpret_cast<uint2*>(L.WTpk + pk_off(n0 + ic, m0 + o0, L.wo)) = make_uint2(lo, hi);
@@ -772,7 +791,10 @@ hipError_t launch_wgrad(WgArgs& g, hipStream_t st) {
     g.bias_block0 = blocks;
     int bias_blocks = 0;
     for (int l = 0; l < g.n_layers; ++l) bias_blocks += (g.L[l].wo + 63) / 64;
-    hipLaunchKernelGGL(wgrad_kernel, dim3(blocks + bias_blocks), dim3(256), 0, st, g);
+    if (blocks <= 1024)
+        hipLaunchKernelGGL(wgrad_kernel<8>, dim3(blocks + bias_blocks), dim3(512), 0, st, g);
+    else
+        hipLaunchKernelGGL(wgrad_kernel<4>, dim3(blocks + bias_blocks), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
