@@ -252,8 +252,11 @@ __device__ __forceinline__ void run_steps(State<EM, SM>& st, const StepCtx& x,
     (void)(omp_step<KKs, EM, SM, G>(st, x) && ...);
 }
 
+// Two waves per SIMD (at most 256 registers per lane), except where a lane holds 16 x 16 or more
+// directions: those tiles get one wave per SIMD, so that the AGPRs can hold what does not fit in
+// the 256 VGPRs (no scratch: measured 2x faster at K=1024, s=16 than the spilling two-wave build).
 template <int EM, int SM, int G, int TT>
-__global__ __launch_bounds__(256, 2) void omp_fused(OmpArgs a) {
+__global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpArgs a) {
     constexpr int T = 16 * TT;
     constexpr int GPW = 64 / G;          // signal groups per wave
     constexpr int SPP = 4 * GPW;         // signals per pass of the 4 waves
