@@ -290,6 +290,13 @@ smdl_status smdl_get_tile(smdl_t h, int m, int K, int s_max, int* lanes_per_sign
 
 /* Force a tile for (K, s_max) (lanes 16/32/64; signals per item 16/32/64). */
 smdl_status smdl_set_tile(smdl_t h, int K, int s_max, int lanes_per_signal, int signals_per_item);
+/*
+ * Factorisation of the MOD normal equations (the FP64 Cholesky solve of the update of Section 1):
+ * 0 (default) picks by the number of dictionaries in the call, 1 forces the multi-work-group
+ * panel factorisation (two launches per 32 columns), 2 one work group per dictionary.  Both give
+ * the same dictionaries up to rounding.  SMDL_E_ARG for another mode.
+ */
+smdl_status smdl_set_mod_solver(smdl_t h, int mode);
 /* Enable (default) or disable automatic tuning on the first learning call of a shape. */
 smdl_status smdl_set_autotune(smdl_t h, int enabled);
 /* Wall time (ms) of the last smdl_split_merge_learn: local phase, merge phase, final coding. */

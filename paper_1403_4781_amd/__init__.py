@@ -89,6 +89,7 @@ def _load():
         "smdl_tune": [vp, vp, i32, i32, vp, i64, i32],
         "smdl_get_tile": [vp, i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)],
         "smdl_set_tile": [vp, i32, i32, i32, i32],
+        "smdl_set_mod_solver": [vp, i32],
         "smdl_set_autotune": [vp, i32],
         "smdl_phase_ms": [vp, C.POINTER(C.c_float)],
         "smdl_last_kernel_ms": [vp, C.POINTER(C.c_float)],
@@ -321,6 +322,10 @@ class Handle:
 
     def set_tile(self, K: int, s_max: int, lanes: int, signals_per_item: int):
         self._check(lib().smdl_set_tile(self._h, K, s_max, lanes, signals_per_item))
+
+    def set_mod_solver(self, mode: int):
+        """0 automatic, 1 multi-work-group panels, 2 one work group per dictionary."""
+        self._check(lib().smdl_set_mod_solver(self._h, mode))
 
     def set_autotune(self, enabled: bool):
         self._check(lib().smdl_set_autotune(self._h, 1 if enabled else 0))

@@ -202,8 +202,9 @@ __global__ void sum_reduce_kernel(double* __restrict__ arena, const double* __re
 // FP64 Cholesky factorisation of the augmented matrix [A; B] (one block per dictionary)
 // ------------------------------------------------------------------------------------------
 // status[8*t + 0] = unused atoms (this call), [1] |= ridge used, [2] |= failed, [3] |= bad codes,
-// [4] = failed in this call (read by the solve and normalisation kernels).  The caller zeroes
-// the status array before a sequence of updates.
+// [4] = failed in this call (read by the solve and normalisation kernels), [5] = a pivot of the
+// multi-work-group factorisation was rejected in this call (the dictionary is factored again by
+// this kernel).  The caller zeroes the status array before a sequence of updates.
 //
 // W (column-major, ld = Kpad + m) holds [A; B]; A = L L^T is factored in place and the B rows are
 // carried along as extra rows of every panel, so that they end as Z = B L^{-T} (the forward half
@@ -242,8 +243,11 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// retry_only: factor only the dictionaries whose multi-work-group factorisation rejected a pivot
+// (status[8*t + 5]), from the products again, with the ridge retry of this kernel.
 __global__ __launch_bounds__(CT) void chol_factor_kernel(const ModDesc* __restrict__ md, int m,
-                                                         int32_t* __restrict__ status) {
+                                                         int32_t* __restrict__ status, int retry_only) {
+    if (retry_only && !status[8 * blockIdx.x + 5]) return;
     const ModDesc d = md[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int Kp = d.Kpad;
@@ -544,6 +548,378 @@ __global__ __launch_bounds__(TCS) void tri_solve_kernel(const ModDesc* __restric
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Multi-work-group factorisation and substitution (dictionaries too few to fill the chip)
+// ------------------------------------------------------------------------------------------
+// The same right-looking Cholesky of [A; B] as above, in panels of PW = 32 columns with two
+// launches per panel, so that every step spreads over many compute units:
+//   chol_setup:  W = [A; B] with identity diagonals on unused atoms; work group 0 of each
+//                dictionary also factors the first 32 x 32 diagonal block;
+//   chol_panel:  every row below the factored diagonal block (A rows and B rows) solves
+//                x L_kk^T = w, one row per thread; A rows are also written mirrored;
+//   chol_update: the trailing lower triangle of A and the trailing B rows, in 64 x 64 tiles on
+//                the FP64 matrix cores (one 32 x 32 quarter per wave); the work group of the
+//                first tile, which holds the next diagonal block, factors that block after
+//                its update.
+// On output W holds the same layout as after chol_factor_kernel: L in the lower triangle and
+// mirrored above it, Z = B L^{-T} in the B rows.  A rejected pivot sets status[8*t + 5]; later
+// launches skip that dictionary and chol_factor_kernel (retry_only) factors it again with its
+// ridge retry.  tri_solve_rows then solves D L = Z with one work group per 16 rows of D.
+constexpr int PW = 32;                       // panel width
+constexpr int UT = 64;                       // trailing-update tile (rows and columns)
+constexpr int SETUP_COLS = PW;               // columns copied by work group 0 of chol_setup
+
+struct DiagBlock {
+    double L[PW][PW + 1];                    // L[r][c], lower triangle
+    double rd[PW];                           // 1 / L[c][c]
+    double dref[PW];                         // pivot reference: the original diagonal entries
+    double colb[16];
+    int bad;
+};
+
+// Factor the 32 x 32 lower block in s.L in place (256 threads, uniform call): two leaves of 16
+// columns, each factored by wave 0 with one row per lane (the finished column broadcast through
+// LDS), with the second leaf's rows solved against the first and its block updated in between.
+__device__ __forceinline__ void factor_diag32(DiagBlock& s, int tid) {
+    const int lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s.bad = 0;
+    __syncthreads();
+#pragma unroll 1
+    for (int leaf = 0; leaf < 2; ++leaf) {
+        const int o = 16 * leaf;
+        if (wave == 0) {
+            // lanes 16..63 repeat lanes 0..15; entries above a row's diagonal are don't-care
+            const int li = lane & 15;
+            double a[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = s.L[o + li][o + c];
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const double djj = readlane_f64(a[j], j);
+                const bool b = !(djj > PIV_TOL * s.dref[o + j]);
+                bad |= b;
+                const double dj = b ? 1.0 : sqrt(djj);
+                const double rd = 1.0 / dj;
+                a[j] *= rd;                               // lane j: d_j; lanes i > j: L[i][j]
+                s.colb[li] = a[j];
+                if (lane == 0) s.rd[o + j] = rd;
+#pragma unroll
+                for (int c = j + 1; c < 16; ++c) a[c] = fma(-a[j], s.colb[c], a[c]);
+            }
+            if (lane == 0 && bad) s.bad = 1;
+            if (lane < 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) s.L[o + lane][o + c] = a[c];
+            }
+        }
+        __syncthreads();
+        if (leaf == 1) break;
+        // rows 16..31 against the first leaf: x L_00^T = w
+        if (tid < 16) {
+            double x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) x[c] = s.L[16 + tid][c];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                x[c] *= s.rd[c];
+#pragma unroll
+                for (int c2 = c + 1; c2 < 16; ++c2) x[c2] = fma(-x[c], s.L[c2][c], x[c2]);
+                __asm__ volatile("" ::: "memory");         // keep column c's LDS reads in this step
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) s.L[16 + tid][c] = x[c];
+        }
+        __syncthreads();
+        // the second leaf's block: L[16 + i][16 + j] -= sum_c L[16 + i][c] L[16 + j][c]
+        {
+            const int i = tid >> 4, j = tid & 15;
+            double v = s.L[16 + i][16 + j];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) v = fma(-s.L[16 + i][c], s.L[16 + j][c], v);
+            __syncthreads();
+            if (j <= i) s.L[16 + i][16 + j] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// The factored block to W at (kb, kb): L below and on the diagonal, its mirror above.
+__device__ __forceinline__ void store_diag32(double* W, int ld, int kb, const DiagBlock& s, int tid) {
+    for (int f = tid; f < PW * PW; f += 256) {
+        const int c = f / PW, r = f % PW;
+        gst(W, 8u * (uint32_t)((kb + c) * ld + kb + r), r >= c ? s.L[r][c] : s.L[c][r]);
+    }
+}
+
+// Pivot references of the block at kb: the products' diagonal, 1 for unused atoms.
+__device__ __forceinline__ void load_dref(DiagBlock& s, const double* P, int ld, int kb, int tid) {
+    if (tid < PW) {
+        const double v = P[(int64_t)(kb + tid) * ld + kb + tid];
+        s.dref[tid] = v > 0.0 ? v : 1.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void chol_setup_kernel(const ModDesc* __restrict__ md, int m,
+                                                         int32_t* __restrict__ status) {
+    const int t = blockIdx.y;
+    const ModDesc d = md[t];
+    const int Kp = d.Kpad, ld = Kp + m, tid = threadIdx.x;
+    const double* P = d.A;
+    double* W = d.W;
+    // work group 0: the first SETUP_COLS columns; the others: the rest, strided
+    int64_t f0, f1, step;
+    if (blockIdx.x == 0) {
+        f0 = tid; f1 = (int64_t)SETUP_COLS * ld; step = 256;
+    } else {
+        f0 = (int64_t)SETUP_COLS * ld + (int64_t)(blockIdx.x - 1) * 256 + tid;
+        f1 = (int64_t)Kp * ld;
+        step = (int64_t)(gridDim.x - 1) * 256;
+    }
+    for (int64_t f = f0; f < f1; f += step) {
+        const int col = (int)(f / ld), row = (int)(f - (int64_t)col * ld);
+        double x = P[f];
+        if (row == col && !(x > 0.0)) x = 1.0;
+        W[f] = x;
+    }
+    if (blockIdx.x != 0) return;
+    __shared__ DiagBlock s;
+    __shared__ int s_cnt[4];
+    int unused = 0;
+    for (int a = tid; a < d.K; a += 256) unused += !(P[(int64_t)a * ld + a] > 0.0);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) unused += __shfl_xor(unused, off, 64);
+    if ((tid & 63) == 0) s_cnt[tid >> 6] = unused;
+    load_dref(s, P, ld, 0, tid);
+    for (int f = tid; f < PW * PW; f += 256) {
+        const int c = f / PW, r = f % PW;
+        double x = P[(int64_t)c * ld + r];
+        if (r == c && !(x > 0.0)) x = 1.0;
+        s.L[r][c] = x;
+    }
+    factor_diag32(s, tid);                   // synchronises before reading s_cnt
+    store_diag32(W, ld, 0, s, tid);
+    if (tid == 0) {
+        int32_t* st = status + 8 * t;
+        st[0] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        st[4] = 0;
+        st[5] = s.bad;
+    }
+}
+
+__global__ __launch_bounds__(256) void chol_panel_kernel(const ModDesc* __restrict__ md, int m,
+                                                         const int32_t* __restrict__ status, int kb) {
+    const int t = blockIdx.y;
+    const ModDesc d = md[t];
+    const int Kp = d.Kpad;
+    if (kb >= Kp || status[8 * t + 5]) return;
+    const int ld = Kp + m, tid = threadIdx.x;
+    double* W = d.W;
+    __shared__ double L[PW][PW + 1];
+    __shared__ double rd[PW];
+    for (int f = tid; f < PW * PW; f += 256) {
+        const int c = f / PW, r = f % PW;
+        L[r][c] = r >= c ? gld(W, 8u * (uint32_t)((kb + c) * ld + kb + r)) : 0.0;
+    }
+    if (tid < PW) rd[tid] = 1.0 / gld(W, 8u * (uint32_t)((kb + tid) * ld + kb + tid));
+    __syncthreads();
+    const int i = kb + PW + blockIdx.x * 256 + tid;
+    if (i >= ld) return;
+    double x[PW];
+#pragma unroll
+    for (int c = 0; c < PW; ++c) x[c] = gld(W, 8u * (uint32_t)((kb + c) * ld + i));
+#pragma unroll
+    for (int c = 0; c < PW; ++c) {
+        x[c] *= rd[c];
+#pragma unroll
+        for (int c2 = c + 1; c2 < PW; ++c2) x[c2] = fma(-x[c], L[c2][c], x[c2]);
+        __asm__ volatile("" ::: "memory");             // keep column c's LDS reads in this step
+    }
+#pragma unroll
+    for (int c = 0; c < PW; ++c) gst(W, 8u * (uint32_t)((kb + c) * ld + i), x[c]);
+    if (i < Kp) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c) gst(W, 8u * (uint32_t)(i * ld + kb + c), x[c]);   // mirror
+    }
+}
+
+// Tiles of the trailing update after the panel at kb: the lower triangle of the A block in
+// UT x UT tiles, then the B rows (UT rows per tile) against every A column tile.
+__host__ __device__ inline int update_tiles(int Kp, int m, int kb) {
+    const int r0 = kb + PW;
+    if (r0 >= Kp) return 0;
+    const int TA = (Kp - r0 + UT - 1) / UT;
+    return TA * (TA + 1) / 2 + (m + UT - 1) / UT * TA;
+}
+
+__global__ __launch_bounds__(256) void chol_update_kernel(const ModDesc* __restrict__ md, int m,
+                                                          int32_t* __restrict__ status, int kb) {
+    const int t = blockIdx.y;
+    const ModDesc d = md[t];
+    const int Kp = d.Kpad;
+    const int tile = blockIdx.x;
+    if (tile >= update_tiles(Kp, m, kb) || status[8 * t + 5]) return;
+    const int ld = Kp + m, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* W = d.W;
+    const int r0 = kb + PW;
+    const int TA = (Kp - r0 + UT - 1) / UT;
+    const int nA = TA * (TA + 1) / 2;
+    int ib, jb, rowbase, rowlim;
+    const bool isA = tile < nA;
+    if (isA) {
+        ib = (int)((sqrtf(8.f * tile + 1.f) - 1.f) * 0.5f);
+        while ((ib + 1) * (ib + 2) / 2 <= tile) ++ib;
+        while (ib * (ib + 1) / 2 > tile) --ib;
+        jb = tile - ib * (ib + 1) / 2;
+        rowbase = r0 + UT * ib;
+        rowlim = Kp;
+    } else {
+        ib = (tile - nA) / TA;
+        jb = (tile - nA) % TA;
+        rowbase = Kp + UT * ib;
+        rowlim = ld;
+    }
+    const bool first = tile == 0;            // holds the next diagonal block (A, ib = jb = 0)
+    __shared__ DiagBlock s;
+    const int qr = wave >> 1, qc = wave & 1;
+    const bool diag_tile = isA && ib == jb;
+    const int R = rowbase + 32 * qr, C = r0 + UT * jb + 32 * qc;
+    const bool wave_on = !(diag_tile && qc > qr) && R < rowlim && C < Kp;
+    if (wave_on) {
+        const int kq = lane >> 4, li = lane & 15;
+        bool blk[2][2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+                blk[rb][cb] = R + 16 * rb < rowlim && C + 16 * cb < Kp && !(diag_tile && qr == qc && cb > rb);
+        const bool to_lds = first && qr == 0 && qc == 0;
+        double av[2][PW / 4], bv[2][PW / 4];
+        double old[2][2][4];
+#pragma unroll
+        for (int u = 0; u < PW / 4; ++u) {
+            const uint32_t colk = (uint32_t)(kb + 4 * u + kq) * ld;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) av[cb][u] = gld(W, 8u * (colk + min(C + 16 * cb + li, Kp - 1)));
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) bv[rb][u] = gld(W, 8u * (colk + min(R + 16 * rb + li, rowlim - 1)));
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int row = R + 16 * rb + li;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    old[rb][cb][q] = blk[rb][cb] && row < rowlim
+                        ? gld(W, 8u * (uint32_t)((C + 16 * cb + kq + 4 * q) * ld + row)) : 0.0;
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int row = R + 16 * rb + li;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                if (!blk[rb][cb]) continue;
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int u = 0; u < PW / 4; ++u)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cb][u], bv[rb][u], acc, 0, 0, 0);
+                // acc[q]: the update of W at row R + 16 rb + li, column C + 16 cb + kq + 4 q
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double v = old[rb][cb][q] - acc[q];
+                    if (to_lds) s.L[16 * rb + li][16 * cb + kq + 4 * q] = v;
+                    else if (row < rowlim) gst(W, 8u * (uint32_t)((C + 16 * cb + kq + 4 * q) * ld + row), v);
+                }
+            }
+        }
+    }
+    if (!first) return;
+    load_dref(s, d.A, ld, r0, tid);
+    factor_diag32(s, tid);                   // synchronises before reading s.L
+    store_diag32(W, ld, r0, s, tid);
+    if (tid == 0 && s.bad) status[8 * t + 5] = 1;
+}
+
+// D L = Z for 16 rows of D per work group: block columns of SB from the last; the product
+// D_{>J} L_{>J,J} of the 16 rows is split over the four waves by k and summed in LDS, then 16
+// threads solve the 32 x 32 triangle of the block column, one row of D each.
+__global__ __launch_bounds__(256) void tri_solve_rows_kernel(const ModDesc* __restrict__ md, int m,
+                                                             const int32_t* __restrict__ status) {
+    const int t = blockIdx.y;
+    if (status[8 * t + 4]) return;
+    const ModDesc d = md[t];
+    const int Kp = d.Kpad, ld = Kp + m;
+    double* W = d.W;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rb0 = 16 * blockIdx.x;
+    const int kq = lane >> 4, li = lane & 15;
+    __shared__ double Lj[SB][SB + 1];
+    __shared__ double rd[SB];
+    __shared__ double part[4][2][16][17];
+    __shared__ double Tt[16][SB + 1];
+    const uint32_t zrow = (uint32_t)(Kp + min(rb0 + li, m - 1));     // this lane's row of D (clamped)
+    for (int J = Kp - SB; J >= 0; J -= SB) {
+        for (int f = tid; f < SB * SB; f += 256) {
+            const int c = f / SB, r = f % SB;
+            Lj[r][c] = r >= c ? gld(W, 8u * (uint32_t)((J + c) * ld + J + r)) : 0.0;
+        }
+        if (tid < SB) rd[tid] = 1.0 / gld(W, 8u * (uint32_t)((J + tid) * ld + J + tid));
+        const int kw = (Kp - J - SB) / 4;                         // a multiple of 8
+        const int kbeg = J + SB + wave * kw;
+        f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < kw; k0 += 32) {
+            double av[8], b0[8], b1[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = kbeg + min(k0 + 4 * u, kw - 4) + kq;
+                av[u] = gld(W, 8u * ((uint32_t)i * ld + zrow));                            // D[r][i]
+                b0[u] = gld(W, 8u * (uint32_t)(i * ld + J + li));                          // L[i][J + c]
+                b1[u] = gld(W, 8u * (uint32_t)(i * ld + J + 16 + li));
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (k0 + 4 * u < kw) {
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b0[u], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b1[u], acc1, 0, 0, 0);
+                }
+            }
+        }
+        // acc[q]: row kq + 4 q of the 16, column 16 cb + li of the block column
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            part[wave][0][kq + 4 * q][li] = acc0[q];
+            part[wave][1][kq + 4 * q][li] = acc1[q];
+        }
+        __syncthreads();
+        for (int f = tid; f < 16 * SB; f += 256) {
+            const int r = f & 15, c = f >> 4;
+            if (rb0 + r < m) {
+                double v = gld(W, 8u * (uint32_t)((J + c) * ld + Kp + rb0 + r));
+#pragma unroll
+                for (int w = 0; w < 4; ++w) v -= part[w][c >> 4][r][c & 15];
+                Tt[r][c] = v;
+            }
+        }
+        __syncthreads();
+        if (tid < 16 && rb0 + tid < m) {
+            double x[SB];
+#pragma unroll
+            for (int c = 0; c < SB; ++c) x[c] = Tt[tid][c];
+#pragma unroll
+            for (int c = SB - 1; c >= 0; --c) {
+                x[c] *= rd[c];
+#pragma unroll
+                for (int c2 = 0; c2 < c; ++c2) x[c2] = fma(-x[c], Lj[c][c2], x[c2]);
+                __asm__ volatile("" ::: "memory");
+            }
+#pragma unroll
+            for (int c = 0; c < SB; ++c) gst(W, 8u * (uint32_t)((J + c) * ld + Kp + rb0 + tid), x[c]);
+        }
+        __syncthreads();
+    }
+}
+
 // Unit-normalise the solved atoms and store them (one wave per atom).
 __global__ __launch_bounds__(256) void mod_normalize_kernel(const ModDesc* __restrict__ md, int m,
                                                             const int32_t* __restrict__ status) {
@@ -566,9 +942,16 @@ __global__ __launch_bounds__(256) void mod_normalize_kernel(const ModDesc* __res
 
 }  // namespace
 
+// The multi-work-group solve unless the dictionaries alone fill the chip (one work group each).
+static bool mod_solve_multi(int n_desc, int solver) {
+    if (solver != 0) return solver == 1;
+    return n_desc < 256;
+}
+
 hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atoms, int64_t max_n, int32_t* cnt,
                       int32_t* fill, int32_t* ptr, int32_t* list_sig, float* list_coef, int32_t* status,
-                      int max_kpad, double* arena, double* part, int64_t arena_len, int chunks, hipStream_t st) {
+                      int max_kpad, double* arena, double* part, int64_t arena_len, int chunks, int solver,
+                      hipStream_t st) {
     hipError_t e;
     if (chunks < 1 || (chunks > 1 && !part)) return hipErrorInvalidValue;
     if ((e = launch_zero_i32(cnt, total_atoms, st)) != hipSuccess) return e;
@@ -589,10 +972,31 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
         hipLaunchKernelGGL(sum_reduce_kernel, dim3(g), dim3(256), 0, st, arena, part, arena_len, chunks - 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(tri_solve_kernel, dim3(n_desc), dim3(TCS), 0, st, dev_desc, m, status);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (mod_solve_multi(n_desc, solver)) {
+        const int64_t cells = (int64_t)(max_kpad - SETUP_COLS) * (max_kpad + m);
+        const unsigned sg = 1 + (unsigned)std::min<int64_t>(63, std::max<int64_t>(1, (cells + 4095) / 4096));
+        hipLaunchKernelGGL(chol_setup_kernel, dim3(sg, n_desc), dim3(256), 0, st, dev_desc, m, status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int kb = 0; kb < max_kpad; kb += PW) {
+            const unsigned pg = (unsigned)((max_kpad + m - kb - PW + 255) / 256);
+            hipLaunchKernelGGL(chol_panel_kernel, dim3(pg, n_desc), dim3(256), 0, st, dev_desc, m, status, kb);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            const int nt = update_tiles(max_kpad, m, kb);
+            if (nt > 0) {
+                hipLaunchKernelGGL(chol_update_kernel, dim3(nt, n_desc), dim3(256), 0, st, dev_desc, m, status, kb);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+        }
+        hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status, 1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(tri_solve_rows_kernel, dim3((m + 15) / 16, n_desc), dim3(256), 0, st, dev_desc, m, status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(tri_solve_kernel, dim3(n_desc), dim3(TCS), 0, st, dev_desc, m, status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(mod_normalize_kernel, dim3((max_kpad + 3) / 4, n_desc), dim3(256), 0, st, dev_desc, m, status);
     return hipGetLastError();
 }

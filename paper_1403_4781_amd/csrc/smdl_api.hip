@@ -422,6 +422,7 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
     plan.max_n = max_n;
     plan.n_desc = (int)specs.size();
     plan.m = m;
+    plan.solver = h->mod_solver;
     double* A = (double*)h->ws((t + ".A").c_str(), abytes);
     double* W = (double*)h->ws((t + ".W").c_str(), abytes);
     plan.cnt = (int32_t*)h->ws((t + ".cnt").c_str(), (total_atoms + 1) * 4);
@@ -461,7 +462,7 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
 hipError_t enqueue_mod(smdl_t h, const ModPlan& plan) {
     return launch_mod(plan.desc, plan.n_desc, plan.m, plan.total_atoms, plan.max_n, plan.cnt, plan.fill, plan.ptr,
                       plan.list_sig, plan.list_coef, plan.status, plan.maxKpad, plan.arena, plan.part,
-                      plan.arena_len, plan.chunks, h->stream);
+                      plan.arena_len, plan.chunks, plan.solver, h->stream);
 }
 
 // Read the MOD status array; returns SMDL_E_NUMERIC / SMDL_E_ARG on failures.
@@ -927,6 +928,13 @@ extern "C" smdl_status smdl_set_tile(smdl_t h, int K, int s_max, int lanes, int 
         return h->fail(SMDL_E_UNSUPPORTED, "tile not instantiated for this shape");
     h->tiles[std::make_tuple(pad64(K), s_max, 0)] = t;
     h->tiles[std::make_tuple(pad64(K), s_max, 1)] = t;
+    return SMDL_OK;
+}
+
+extern "C" smdl_status smdl_set_mod_solver(smdl_t h, int mode) {
+    if (!h) return SMDL_E_ARG;
+    if (mode < 0 || mode > 2) return h->fail(SMDL_E_ARG, "MOD solver mode must be 0, 1 or 2");
+    h->mod_solver = mode;
     return SMDL_OK;
 }
 

@@ -28,6 +28,7 @@ struct smdl_ctx {
     std::map<std::string, Buf> bufs;
     std::map<std::tuple<int, int, int>, OmpTile> tiles;
     bool autotune = true;
+    int mod_solver = 0;                         // 0 automatic, 1 multi-work-group, 2 one work group
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed_pending = false;
     float last_kernel_ms = 0.f;
@@ -95,6 +96,7 @@ struct ModPlan {
     double *arena = nullptr, *part = nullptr;   // products workspace and its partial copies
     int64_t arena_len = 0;                      // doubles
     int chunks = 1;                             // blocks per atom in the products
+    int solver = 0;                             // the handle's mod_solver
     std::vector<ModDesc> host_desc;
 };
 

@@ -116,10 +116,12 @@ struct ModDesc {
 // The MOD chain for n_desc dictionaries.  arena: the products workspace M = [A; B] of every
 // descriptor (arena_len doubles, the descriptors' A pointers inside it); with chunks > 1 every
 // atom's products are split over that many blocks and part holds (chunks - 1) x arena_len
-// doubles of partial sums.
+// doubles of partial sums.  solver: 0 picks the factorisation by the number of dictionaries,
+// 1 forces the multi-work-group panels, 2 one work group per dictionary.
 hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atoms, int64_t max_n, int32_t* cnt,
                       int32_t* fill, int32_t* ptr, int32_t* list_sig, float* list_coef, int32_t* status,
-                      int max_kpad, double* arena, double* part, int64_t arena_len, int chunks, hipStream_t st);
+                      int max_kpad, double* arena, double* part, int64_t arena_len, int chunks, int solver,
+                      hipStream_t st);
 
 // Misc kernels.
 hipError_t launch_gather_columns(const float* Y, const int64_t* perm, int64_t N, int m, float* out,

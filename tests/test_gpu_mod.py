@@ -41,24 +41,66 @@ def _f32codes(codes):
     return oracle.Codes(codes.idx.copy(), codes.coef.astype(np.float32).astype(np.float64), codes.nnz.copy())
 
 
+class _solver:
+    """Force the handle's MOD factorisation (1 multi-work-group panels, 2 one work group per
+    dictionary) for the duration of a block."""
+    def __init__(self, h, mode):
+        self.h, self.mode = h, mode
+
+    def __enter__(self):
+        self.h.set_mod_solver(self.mode)
+
+    def __exit__(self, *exc):
+        self.h.set_mod_solver(0)
+
+
+@pytest.mark.parametrize("solver", [1, 2])
 @pytest.mark.parametrize("m,K,s,N", [(64, 128, 5, 2000), (64, 256, 8, 5000), (30, 60, 6, 1000),
                                      (256, 512, 16, 3000), (64, 192, 12, 2500)])
-def test_mod_teacher_forced(h, dev, m, K, s, N):
-    print(f"case mod m={m} K={K} s={s} N={N}", flush=True)
+def test_mod_teacher_forced(h, dev, m, K, s, N, solver):
+    print(f"case mod m={m} K={K} s={s} N={N} solver={solver}", flush=True)
     D, Y, _ = synth.small_problem(3000 + K + s, m, K, min(s, 8), 0.02, N)
     codes = _f32codes(oracle.omp(D, Y, s))
     Dref, nu_ref, _ = oracle.mod_update(Y, codes, D)
     Dg = _t(D, dev)
-    nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+    with _solver(h, solver):
+        nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
     err = np.linalg.norm(Dg.cpu().numpy() - Dref, axis=1).max()
     print(f"  max atom error {err:.3e} unused {nu}/{nu_ref}", flush=True)
     assert nu == nu_ref
     assert err <= D_TOL
 
 
-def test_mod_unused_atoms_and_ridge(h, dev):
-    """Unused atoms keep their value; two atoms used identically trigger the ridge retry."""
-    print("case mod ridge", flush=True)
+def test_mod_large_dictionary_both_solvers(h, dev):
+    """K=1024, m=256 (the merged dictionary of the large workload) from random codes with s=16:
+    both factorisations match the oracle to the MOD bar and each other to 1e-6."""
+    print("case mod m=256 K=1024 s=16 N=20000", flush=True)
+    rng = np.random.default_rng(3300)
+    m, K, s, N = 256, 1024, 16, 20000
+    Y = rng.standard_normal((N, m)).astype(np.float32)
+    idx = np.argsort(rng.random((N, K)), axis=1)[:, :s].astype(np.int32)
+    coef = rng.standard_normal((N, s)).astype(np.float32).astype(np.float64)
+    codes = oracle.Codes(idx, coef, np.full(N, s, np.int32))
+    D = synth.gaussian_dictionary(rng, m, K).astype(np.float32)
+    Dref, nu_ref, _ = oracle.mod_update(Y, codes, D)
+    out = {}
+    for solver in (1, 2):
+        Dg = _t(D, dev)
+        with _solver(h, solver):
+            nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+        out[solver] = Dg.cpu().numpy()
+        err = np.linalg.norm(out[solver] - Dref, axis=1).max()
+        print(f"  solver {solver}: max atom error {err:.3e} unused {nu}/{nu_ref}", flush=True)
+        assert nu == nu_ref == 0
+        assert err <= D_TOL
+    assert np.linalg.norm(out[1] - out[2], axis=1).max() <= 1e-6
+
+
+@pytest.mark.parametrize("solver", [1, 2])
+def test_mod_unused_atoms_and_ridge(h, dev, solver):
+    """Unused atoms keep their value; two atoms used identically trigger the ridge retry (with
+    the multi-work-group panels: their rejected pivot hands the dictionary to the retry)."""
+    print(f"case mod ridge solver={solver}", flush=True)
     rng = np.random.default_rng(3100)
     m, K, N = 16, 64, 400
     Y = rng.standard_normal((N, m)).astype(np.float32)
@@ -74,7 +116,8 @@ def test_mod_unused_atoms_and_ridge(h, dev):
     Dref, nu_ref, ridge = oracle.mod_update(Y, codes, D)
     assert ridge == 1 and nu_ref == K - 12
     Dg = _t(D, dev)
-    nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+    with _solver(h, solver):
+        nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
     Dn = Dg.cpu().numpy()
     assert nu == nu_ref
     np.testing.assert_array_equal(Dn[12:], D[12:])
@@ -187,16 +230,19 @@ def test_batched_uneven_subsets(h, dev):
     perm = torch.from_numpy(w.perm).to(dev)
     Yt = _t(w.Y, dev)
     res = {}
-    for flags in (0, 1):
-        print(f"case batched uneven flags={flags}", flush=True)
-        D, X, Dl, sc = h.split_merge_learn(Yt, perm, w.offsets, Kl, sl, w.K, 2, 1, 4, 8, flags=flags, local=True)
-        res[flags] = (Dl.cpu().numpy(), sc)
+    for flags, solver in ((0, 0), (1, 0), (0, 2)):
+        print(f"case batched uneven flags={flags} solver={solver}", flush=True)
+        with _solver(h, solver):
+            D, X, Dl, sc = h.split_merge_learn(Yt, perm, w.offsets, Kl, sl, w.K, 2, 1, 4, 8, flags=flags,
+                                               local=True)
+        res[flags, solver] = (Dl.cpu().numpy(), sc)
     ao = np.concatenate([[0], np.cumsum(Kl)])
-    for t in range(L):
-        a = res[0][0][ao[t]:ao[t + 1]]
-        b = res[1][0][ao[t]:ao[t + 1]]
-        assert np.linalg.norm(a - b, axis=1).max() <= 1e-3
-    np.testing.assert_allclose(res[0][1], res[1][1], rtol=1e-4)
+    for other in ((1, 0), (0, 2)):      # per-subset launches; one work group per factorisation
+        for t in range(L):
+            a = res[0, 0][0][ao[t]:ao[t + 1]]
+            b = res[other][0][ao[t]:ao[t + 1]]
+            assert np.linalg.norm(a - b, axis=1).max() <= 1e-3
+        np.testing.assert_allclose(res[0, 0][1], res[other][1], rtol=1e-4)
     # iteration 0 of every subset against the oracle
     for t in range(L):
         sub = w.Y[w.perm[w.offsets[t]:w.offsets[t + 1]]]
