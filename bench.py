@@ -379,6 +379,39 @@ def run_denoise(args, smdl, synth, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_modsolve(args, smdl, synth, torch, dev):
+    """The MOD update at the shapes of the workloads, with each factorisation of the normal
+    equations forced in turn (2: one work group per dictionary, 1: multi-work-group panels): one
+    JSON line per shape with the wall time of one smdl_mod_update (transpose, products, solve,
+    normalisation; mean of 10 after one warm-up) and the largest difference of the two results."""
+    h = smdl.Handle(0)
+    rng = np.random.default_rng(synth.SEED_BASE + 300)
+    shapes = [("merge, patch scale", 64, 256, 4, 5120), ("local, patch scale", 64, 256, 8, 5000),
+              ("local, large", 256, 512, 16, 10000), ("merge, large", 256, 1024, 8, 51200),
+              ("synthetic experiment", 30, 64, 6, 1000)]
+    for name, m, K, s, N in shapes:
+        idx = torch.rand(N, K, device=dev).argsort(dim=1)[:, :s].int().contiguous()
+        X = smdl.Codes(idx, torch.randn(N, s, device=dev), torch.full((N,), s, dtype=torch.int32, device=dev))
+        Y = torch.randn(N, m, device=dev)
+        D0 = torch.from_numpy(synth.gaussian_dictionary(rng, m, K).astype(np.float32)).to(dev)
+        res = {}
+        for solver in (2, 1):
+            h.set_mod_solver(solver)
+            D = D0.clone()
+            h.mod_update(Y, X, D)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                D = D0.clone()
+                h.mod_update(Y, X, D)
+            torch.cuda.synchronize()
+            res[solver] = ((time.perf_counter() - t0) / 10 * 1e3, D.cpu().numpy())
+        h.set_mod_solver(0)
+        print(json.dumps({"shape": name, "m": m, "K": K, "s": s, "N": N,
+                          "one_work_group_ms": round(res[2][0], 3), "multi_work_group_ms": round(res[1][0], 3),
+                          "max_abs_difference": float(np.abs(res[1][1] - res[2][1]).max())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,9 +432,10 @@ def main():
     ap.add_argument("--trials", type=int, default=20, help="e1: independent trials")
     ap.add_argument("--e1-iters", type=int, default=100, help="e1: iterations of every learning stage")
     ap.add_argument("--e1-oracle-trials", type=int, default=1, help="e1: trials also run by the FP64 oracle")
-    ap.add_argument("--config", default="split_merge", choices=["split_merge", "batched", "large", "e1", "denoise"],
+    ap.add_argument("--config", default="split_merge", choices=["split_merge", "batched", "large", "e1", "denoise", "modsolve"],
                     help="batched: the 64-subset uneven split phase, batched vs per-subset launches; "
-                         "large: m=256, K=1024, N=1e6 with the 256-1024-1024-1024 proposer (one JSON line each)")
+                         "large: m=256, K=1024, N=1e6 with the 256-1024-1024-1024 proposer (one JSON line each); "
+                         "modsolve: the MOD update with each factorisation forced (one JSON line per shape)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -425,6 +459,9 @@ def main():
         return
     if args.config == "denoise":
         run_denoise(args, smdl, synth, torch, dev)
+        return
+    if args.config == "modsolve":
+        run_modsolve(args, smdl, synth, torch, dev)
         return
     if args.copy_calib:
         n = args.copy_calib * (1 << 20) // 4

@@ -141,8 +141,12 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
     const int a = blockIdx.x;
     const int c = blockIdx.z, P = gridDim.z;
     if (a >= d.Kpad) return;
+    constexpr int PSTAGE = 512;              // list entries staged per pass
+    constexpr int PB = 8;                    // signal loads in flight per thread
     __shared__ double colA[SMDL_MAX_K];
     __shared__ double partB[8][SMDL_MAX_M];
+    __shared__ int32_t s_sig[PSTAGE];
+    __shared__ float s_cf[PSTAGE];
     const int tid = threadIdx.x;
     for (int l = tid; l < d.Kpad; l += 256) colA[l] = 0.0;
     __syncthreads();
@@ -156,24 +160,39 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
         const int lb = ptr[ga], le = ptr[ga + 1];
         const int len = (le - lb + P - 1) / P;
         const int b = min(le, lb + c * len), e = min(le, b + len);
-        // A column: every entry (n, x_na) adds x_na * x_nl at every atom l of signal n
-        for (int p = b + tid; p < e; p += 256) {
-            const int64_t n = list_sig[p];
-            const double xa = list_coef[p];
-            const int k = clamp_nnz(d.nnz[n], d.s_stride);
-            for (int i = 0; i < k; ++i) {
-                const int l = d.idx[n * d.s_stride + i];
-                if (l < 0 || l >= d.K) continue;
-                atomicAdd(&colA[l], xa * (double)d.coef[n * d.s_stride + i]);
-            }
-        }
-        // B column: rows split over threads, entries over groups of threads
+        // the entries in passes of PSTAGE, staged in LDS
         double acc = 0.0;
-        if (r < m) {
-#pragma unroll 4
-            for (int p = b + grp; p < e; p += groups) {
-                const int64_t n = list_sig[p];
-                acc += (double)list_coef[p] * (double)d.Y[n * m + r];
+        for (int p0 = b; p0 < e; p0 += PSTAGE) {
+            const int cnt = min(PSTAGE, e - p0);
+            __syncthreads();                                  // the previous pass is read
+            for (int q = tid; q < cnt; q += 256) {
+                s_sig[q] = list_sig[p0 + q];
+                s_cf[q] = list_coef[p0 + q];
+            }
+            __syncthreads();
+            // A column: every entry (n, x_na) adds x_na * x_nl at every atom l of signal n
+            for (int q = tid; q < cnt; q += 256) {
+                const int64_t n = s_sig[q];
+                const double xa = s_cf[q];
+                const int k = clamp_nnz(d.nnz[n], d.s_stride);
+                for (int i = 0; i < k; ++i) {
+                    const int l = d.idx[n * d.s_stride + i];
+                    if (l < 0 || l >= d.K) continue;
+                    atomicAdd(&colA[l], xa * (double)d.coef[n * d.s_stride + i]);
+                }
+            }
+            // B column: rows split over threads, entries over groups of threads, PB signal
+            // loads in flight per thread (the sum keeps the order of the entries)
+            if (r < m) {
+                int q = grp;
+                for (; q + (PB - 1) * groups < cnt; q += PB * groups) {
+                    float yv[PB];
+#pragma unroll
+                    for (int u = 0; u < PB; ++u) yv[u] = d.Y[(int64_t)s_sig[q + u * groups] * m + r];
+#pragma unroll
+                    for (int u = 0; u < PB; ++u) acc += (double)s_cf[q + u * groups] * (double)yv[u];
+                }
+                for (; q < cnt; q += groups) acc += (double)s_cf[q] * (double)d.Y[(int64_t)s_sig[q] * m + r];
             }
         }
         partB[grp][r] = acc;
@@ -554,7 +573,7 @@ __global__ __launch_bounds__(TCS) void tri_solve_kernel(const ModDesc* __restric
 // The same right-looking Cholesky of [A; B] as above, in panels of PW = 32 columns with two
 // launches per panel, so that every step spreads over many compute units:
 //   chol_setup:  W = [A; B] with identity diagonals on unused atoms; work group 0 of each
-//                dictionary also factors the first 32 x 32 diagonal block;
+//                dictionary factors the first 32 x 32 diagonal block (the others copy the rest);
 //   chol_panel:  every row below the factored diagonal block (A rows and B rows) solves
 //                x L_kk^T = w, one row per thread; A rows are also written mirrored;
 //   chol_update: the trailing lower triangle of A and the trailing B rows, in 64 x 64 tiles on
@@ -567,7 +586,6 @@ __global__ __launch_bounds__(TCS) void tri_solve_kernel(const ModDesc* __restric
 // ridge retry.  tri_solve_rows then solves D L = Z with one work group per 16 rows of D.
 constexpr int PW = 32;                       // panel width
 constexpr int UT = 64;                       // trailing-update tile (rows and columns)
-constexpr int SETUP_COLS = PW;               // columns copied by work group 0 of chol_setup
 
 struct DiagBlock {
     double L[PW][PW + 1];                    // L[r][c], lower triangle
@@ -667,22 +685,32 @@ __global__ __launch_bounds__(256) void chol_setup_kernel(const ModDesc* __restri
     const int Kp = d.Kpad, ld = Kp + m, tid = threadIdx.x;
     const double* P = d.A;
     double* W = d.W;
-    // work group 0: the first SETUP_COLS columns; the others: the rest, strided
-    int64_t f0, f1, step;
-    if (blockIdx.x == 0) {
-        f0 = tid; f1 = (int64_t)SETUP_COLS * ld; step = 256;
-    } else {
-        f0 = (int64_t)SETUP_COLS * ld + (int64_t)(blockIdx.x - 1) * 256 + tid;
-        f1 = (int64_t)Kp * ld;
-        step = (int64_t)(gridDim.x - 1) * 256;
+    if (blockIdx.x != 0) {
+        // the copy, sixteen loads in flight per thread; the first 32 x 32 diagonal block is
+        // left to work group 0
+        const int64_t total = (int64_t)Kp * ld;
+        const int64_t stride = (int64_t)(gridDim.x - 1) * 256;
+        for (int64_t f0 = (int64_t)(blockIdx.x - 1) * 256 + tid; f0 < total; f0 += 16 * stride) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int64_t f = f0 + u * stride;
+                v[u] = f < total ? P[f] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int64_t f = f0 + u * stride;
+                if (f < total) {
+                    const int col = (int)(f / ld), row = (int)(f - (int64_t)col * ld);
+                    if (col < PW && row < PW) continue;
+                    double x = v[u];
+                    if (row == col && !(x > 0.0)) x = 1.0;
+                    W[f] = x;
+                }
+            }
+        }
+        return;
     }
-    for (int64_t f = f0; f < f1; f += step) {
-        const int col = (int)(f / ld), row = (int)(f - (int64_t)col * ld);
-        double x = P[f];
-        if (row == col && !(x > 0.0)) x = 1.0;
-        W[f] = x;
-    }
-    if (blockIdx.x != 0) return;
     __shared__ DiagBlock s;
     __shared__ int s_cnt[4];
     int unused = 0;
@@ -717,17 +745,27 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const ModDesc* __restri
     double* W = d.W;
     __shared__ double L[PW][PW + 1];
     __shared__ double rd[PW];
-    for (int f = tid; f < PW * PW; f += 256) {
-        const int c = f / PW, r = f % PW;
-        L[r][c] = r >= c ? gld(W, 8u * (uint32_t)((kb + c) * ld + kb + r)) : 0.0;
-    }
-    if (tid < PW) rd[tid] = 1.0 / gld(W, 8u * (uint32_t)((kb + tid) * ld + kb + tid));
-    __syncthreads();
+    // this thread's row and the factored diagonal block, requested together
     const int i = kb + PW + blockIdx.x * 256 + tid;
-    if (i >= ld) return;
+    const int ic = min(i, ld - 1);
     double x[PW];
 #pragma unroll
-    for (int c = 0; c < PW; ++c) x[c] = gld(W, 8u * (uint32_t)((kb + c) * ld + i));
+    for (int c = 0; c < PW; ++c) x[c] = gld(W, 8u * (uint32_t)((kb + c) * ld + ic));
+    double lv[PW * PW / 256];
+#pragma unroll
+    for (int u = 0; u < PW * PW / 256; ++u) {
+        const int f = tid + 256 * u, c = f / PW, r = f % PW;
+        lv[u] = r >= c ? gld(W, 8u * (uint32_t)((kb + c) * ld + kb + r)) : 0.0;
+    }
+    const double dv = tid < PW ? gld(W, 8u * (uint32_t)((kb + tid) * ld + kb + tid)) : 1.0;
+#pragma unroll
+    for (int u = 0; u < PW * PW / 256; ++u) {
+        const int f = tid + 256 * u;
+        L[f % PW][f / PW] = lv[u];
+    }
+    if (tid < PW) rd[tid] = 1.0 / dv;
+    __syncthreads();
+    if (i >= ld) return;
 #pragma unroll
     for (int c = 0; c < PW; ++c) {
         x[c] *= rd[c];
@@ -842,10 +880,19 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const ModDesc* __restr
 }
 
 // D L = Z for 16 rows of D per work group: block columns of SB from the last; the product
-// D_{>J} L_{>J,J} of the 16 rows is split over the four waves by k and summed in LDS, then 16
-// threads solve the 32 x 32 triangle of the block column, one row of D each.
-__global__ __launch_bounds__(256) void tri_solve_rows_kernel(const ModDesc* __restrict__ md, int m,
-                                                             const int32_t* __restrict__ status) {
+// D_{>J} L_{>J,J} of the 16 rows is split over the TW waves by k and summed in LDS, then 16
+// threads solve the 32 x 32 triangle of the block column, one row of D each.  The diagonal block
+// and the right-hand sides of a block column are requested together with the product's
+// operands, so that each block column waits on global memory about once.  TW: 4 waves when the
+// launch has many work groups, 8 when it has few (more of the product in flight per group;
+// 16 waves measured slower: 452 against 307 us at K = 1024, m = 256).
+template <int TW>
+__global__ __launch_bounds__(64 * TW) void tri_solve_rows_kernel(const ModDesc* __restrict__ md, int m,
+                                                                 const int32_t* __restrict__ status) {
+    constexpr int NT = 64 * TW;
+    constexpr int NL = (SB * SB + NT - 1) / NT;      // diagonal-block entries per thread
+    constexpr int NZ = (16 * SB + NT - 1) / NT;      // right-hand-side entries per thread
+    constexpr int UB = TW == 8 ? 16 : 8;             // MFMA steps per batch of loads
     const int t = blockIdx.y;
     if (status[8 * t + 4]) return;
     const ModDesc d = md[t];
@@ -856,35 +903,51 @@ __global__ __launch_bounds__(256) void tri_solve_rows_kernel(const ModDesc* __re
     const int kq = lane >> 4, li = lane & 15;
     __shared__ double Lj[SB][SB + 1];
     __shared__ double rd[SB];
-    __shared__ double part[4][2][16][17];
+    __shared__ double part[TW][2][16][17];
     __shared__ double Tt[16][SB + 1];
     const uint32_t zrow = (uint32_t)(Kp + min(rb0 + li, m - 1));     // this lane's row of D (clamped)
     for (int J = Kp - SB; J >= 0; J -= SB) {
-        for (int f = tid; f < SB * SB; f += 256) {
-            const int c = f / SB, r = f % SB;
-            Lj[r][c] = r >= c ? gld(W, 8u * (uint32_t)((J + c) * ld + J + r)) : 0.0;
-        }
-        if (tid < SB) rd[tid] = 1.0 / gld(W, 8u * (uint32_t)((J + tid) * ld + J + tid));
-        const int kw = (Kp - J - SB) / 4;                         // a multiple of 8
-        const int kbeg = J + SB + wave * kw;
-        f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < kw; k0 += 32) {
-            double av[8], b0[8], b1[8];
+        double lv[NL], zv[NZ];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < NL; ++u) {
+            const int f = tid + u * NT, c = f / SB, r = f % SB;
+            lv[u] = f < SB * SB && r >= c ? gld(W, 8u * (uint32_t)((J + c) * ld + J + r)) : 0.0;
+        }
+        const double dv = tid < SB ? gld(W, 8u * (uint32_t)((J + tid) * ld + J + tid)) : 1.0;
+#pragma unroll
+        for (int u = 0; u < NZ; ++u) {
+            const int f = tid + u * NT, r = f & 15, c = f >> 4;
+            zv[u] = f < 16 * SB && rb0 + r < m ? gld(W, 8u * (uint32_t)((J + c) * ld + Kp + rb0 + r)) : 0.0;
+        }
+        // this wave's share of the k range, in MFMA steps of 4
+        const int S = (Kp - J - SB) / 4;
+        const int kbeg = J + SB + 4 * (wave * S / TW);
+        const int kw = 4 * ((wave + 1) * S / TW - wave * S / TW);
+        f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < kw; k0 += 4 * UB) {
+            double av[UB], b0[UB], b1[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
                 const int i = kbeg + min(k0 + 4 * u, kw - 4) + kq;
                 av[u] = gld(W, 8u * ((uint32_t)i * ld + zrow));                            // D[r][i]
                 b0[u] = gld(W, 8u * (uint32_t)(i * ld + J + li));                          // L[i][J + c]
                 b1[u] = gld(W, 8u * (uint32_t)(i * ld + J + 16 + li));
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < UB; ++u) {
                 if (k0 + 4 * u < kw) {
                     acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b0[u], acc0, 0, 0, 0);
                     acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b1[u], acc1, 0, 0, 0);
                 }
             }
         }
+        // (the previous block column's solve has finished: the barrier closing its iteration)
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int f = tid + u * NT;
+            if (f < SB * SB) Lj[f % SB][f / SB] = lv[u];
+        }
+        if (tid < SB) rd[tid] = 1.0 / dv;
         // acc[q]: row kq + 4 q of the 16, column 16 cb + li of the block column
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -892,12 +955,13 @@ __global__ __launch_bounds__(256) void tri_solve_rows_kernel(const ModDesc* __re
             part[wave][1][kq + 4 * q][li] = acc1[q];
         }
         __syncthreads();
-        for (int f = tid; f < 16 * SB; f += 256) {
-            const int r = f & 15, c = f >> 4;
-            if (rb0 + r < m) {
-                double v = gld(W, 8u * (uint32_t)((J + c) * ld + Kp + rb0 + r));
 #pragma unroll
-                for (int w = 0; w < 4; ++w) v -= part[w][c >> 4][r][c & 15];
+        for (int u = 0; u < NZ; ++u) {
+            const int f = tid + u * NT, r = f & 15, c = f >> 4;
+            if (f < 16 * SB && rb0 + r < m) {
+                double v = zv[u];
+#pragma unroll
+                for (int w = 0; w < TW; ++w) v -= part[w][c >> 4][r][c & 15];
                 Tt[r][c] = v;
             }
         }
@@ -973,8 +1037,8 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (mod_solve_multi(n_desc, solver)) {
-        const int64_t cells = (int64_t)(max_kpad - SETUP_COLS) * (max_kpad + m);
-        const unsigned sg = 1 + (unsigned)std::min<int64_t>(63, std::max<int64_t>(1, (cells + 4095) / 4096));
+        const int64_t cells = (int64_t)max_kpad * (max_kpad + m);
+        const unsigned sg = 1 + (unsigned)std::min<int64_t>(64, std::max<int64_t>(1, (cells + 4095) / 4096));
         hipLaunchKernelGGL(chol_setup_kernel, dim3(sg, n_desc), dim3(256), 0, st, dev_desc, m, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (int kb = 0; kb < max_kpad; kb += PW) {
@@ -989,7 +1053,12 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
         }
         hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status, 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(tri_solve_rows_kernel, dim3((m + 15) / 16, n_desc), dim3(256), 0, st, dev_desc, m, status);
+        const dim3 tg((m + 15) / 16, n_desc);
+        const int64_t groups = (int64_t)tg.x * n_desc;
+        if (groups >= 512)
+            hipLaunchKernelGGL(tri_solve_rows_kernel<4>, tg, dim3(256), 0, st, dev_desc, m, status);
+        else
+            hipLaunchKernelGGL(tri_solve_rows_kernel<8>, tg, dim3(512), 0, st, dev_desc, m, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
         hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status, 0);
