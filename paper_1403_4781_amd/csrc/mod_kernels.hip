@@ -570,20 +570,21 @@ __global__ __launch_bounds__(TCS) void tri_solve_kernel(const ModDesc* __restric
 // ------------------------------------------------------------------------------------------
 // Multi-work-group factorisation and substitution (dictionaries too few to fill the chip)
 // ------------------------------------------------------------------------------------------
-// The same right-looking Cholesky of [A; B] as above, in panels of PW = 32 columns with two
-// launches per panel, so that every step spreads over many compute units:
+// The same right-looking Cholesky of [A; B] as above, in panels of PW = 32 columns with one
+// launch per panel, so that every step spreads over many compute units:
 //   chol_setup:  W = [A; B] with identity diagonals on unused atoms; work group 0 of each
 //                dictionary factors the first 32 x 32 diagonal block (the others copy the rest);
-//   chol_panel:  every row below the factored diagonal block (A rows and B rows) solves
-//                x L_kk^T = w, one row per thread; A rows are also written mirrored;
+//   chol_panel:  (first panel only) every row below the factored diagonal block, A rows and B
+//                rows, solves x L_kk^T = w, one row per thread; A rows are also written mirrored;
 //   chol_update: the trailing lower triangle of A and the trailing B rows, in 64 x 64 tiles on
-//                the FP64 matrix cores (one 32 x 32 quarter per wave); the work group of the
-//                first tile, which holds the next diagonal block, factors that block after
-//                its update.
-// On output W holds the same layout as after chol_factor_kernel: L in the lower triangle and
-// mirrored above it, Z = B L^{-T} in the B rows.  A rejected pivot sets status[8*t + 5]; later
-// launches skip that dictionary and chol_factor_kernel (retry_only) factors it again with its
-// ridge retry.  tri_solve_rows then solves D L = Z with one work group per 16 rows of D.
+//                the FP64 matrix cores (one 32 x 32 quarter per wave).  The tiles of the first
+//                column block also form and factor the next diagonal block and solve their rows
+//                of the next panel, so that the next launch finds that panel solved.
+// The factored diagonal blocks go to a side array (ModDesc::Ld), not into W, whose diagonal blocks
+// the update launches read.  On output W holds L below the diagonal blocks and mirrored above
+// them, and Z = B L^{-T} in the B rows.  A rejected pivot sets status[8*t + 5]; later launches skip
+// that dictionary and chol_factor_kernel (retry_only) factors it again with its ridge retry (then W
+// holds its whole factor).  tri_solve_rows then solves D L = Z with one work group per 16 rows of D.
 constexpr int PW = 32;                       // panel width
 constexpr int UT = 64;                       // trailing-update tile (rows and columns)
 
@@ -662,11 +663,12 @@ __device__ __forceinline__ void factor_diag32(DiagBlock& s, int tid) {
     }
 }
 
-// The factored block to W at (kb, kb): L below and on the diagonal, its mirror above.
-__device__ __forceinline__ void store_diag32(double* W, int ld, int kb, const DiagBlock& s, int tid) {
+// The factored block at (kb, kb) to the side array Ld (block kb / 32, column-major, zero above the
+// diagonal).
+__device__ __forceinline__ void store_diag_block(double* Ld, int kb, const DiagBlock& s, int tid) {
     for (int f = tid; f < PW * PW; f += 256) {
         const int c = f / PW, r = f % PW;
-        gst(W, 8u * (uint32_t)((kb + c) * ld + kb + r), r >= c ? s.L[r][c] : s.L[c][r]);
+        Ld[(int64_t)kb * PW + f] = r >= c ? s.L[r][c] : 0.0;
     }
 }
 
@@ -726,7 +728,7 @@ __global__ __launch_bounds__(256) void chol_setup_kernel(const ModDesc* __restri
         s.L[r][c] = x;
     }
     factor_diag32(s, tid);                   // synchronises before reading s_cnt
-    store_diag32(W, ld, 0, s, tid);
+    store_diag_block(d.Ld, 0, s, tid);
     if (tid == 0) {
         int32_t* st = status + 8 * t;
         st[0] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
@@ -751,13 +753,11 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const ModDesc* __restri
     double x[PW];
 #pragma unroll
     for (int c = 0; c < PW; ++c) x[c] = gld(W, 8u * (uint32_t)((kb + c) * ld + ic));
+    const double* Lb = d.Ld + (int64_t)kb * PW;
     double lv[PW * PW / 256];
 #pragma unroll
-    for (int u = 0; u < PW * PW / 256; ++u) {
-        const int f = tid + 256 * u, c = f / PW, r = f % PW;
-        lv[u] = r >= c ? gld(W, 8u * (uint32_t)((kb + c) * ld + kb + r)) : 0.0;
-    }
-    const double dv = tid < PW ? gld(W, 8u * (uint32_t)((kb + tid) * ld + kb + tid)) : 1.0;
+    for (int u = 0; u < PW * PW / 256; ++u) lv[u] = Lb[tid + 256 * u];
+    const double dv = tid < PW ? Lb[tid * PW + tid] : 1.0;
 #pragma unroll
     for (int u = 0; u < PW * PW / 256; ++u) {
         const int f = tid + 256 * u;
@@ -790,6 +790,45 @@ __host__ __device__ inline int update_tiles(int Kp, int m, int kb) {
     return TA * (TA + 1) / 2 + (m + UT - 1) / UT * TA;
 }
 
+// The next diagonal block (rows and columns r0 .. r0 + 31) after the update with the panel at kb,
+// into s.L (one wave; the three 16 x 16 blocks on and below the diagonal).  Every lead tile forms
+// it from the same operands in the same MFMA order, so all of them hold the same bits.
+__device__ __forceinline__ void diag_update32(DiagBlock& s, const double* W, int ld, int kb, int r0, int lane) {
+    const int kq = lane >> 4, li = lane & 15;
+    double av[2][PW / 4];
+#pragma unroll
+    for (int u = 0; u < PW / 4; ++u) {
+        const uint32_t colk = (uint32_t)(kb + 4 * u + kq) * ld;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) av[b][u] = gld(W, 8u * (colk + r0 + 16 * b + li));
+    }
+    double old[2][2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb <= rb; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                old[rb][cb][q] = gld(W, 8u * (uint32_t)((r0 + 16 * cb + kq + 4 * q) * ld + r0 + 16 * rb + li));
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb <= rb; ++cb) {
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int u = 0; u < PW / 4; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cb][u], av[rb][u], acc, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s.L[16 * rb + li][16 * cb + kq + 4 * q] = old[rb][cb][q] - acc[q];
+        }
+}
+
+// The trailing update after the panel at kb, fused with the row solves of the next panel.  Tiles
+// of the first column block ("lead" tiles) keep the updated next-panel columns of their 64 rows in
+// LDS, form and factor the next diagonal block themselves, solve their rows against it (written in
+// place and, for A rows, mirrored) and so leave the next panel solved for the next launch.  The
+// work group of the first tile also stores the factored block in the side array Ld.  No work group
+// writes the next diagonal block of W, which the lead tiles read.
 __global__ __launch_bounds__(256) void chol_update_kernel(const ModDesc* __restrict__ md, int m,
                                                           int32_t* __restrict__ status, int kb) {
     const int t = blockIdx.y;
@@ -817,12 +856,14 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const ModDesc* __restr
         rowbase = Kp + UT * ib;
         rowlim = ld;
     }
-    const bool first = tile == 0;            // holds the next diagonal block (A, ib = jb = 0)
+    const bool first = tile == 0;            // A, ib = jb = 0: its first quarter is the next diagonal block
+    const bool lead = jb == 0;
     __shared__ DiagBlock s;
+    __shared__ double T[UT][PW + 1];         // lead tiles: updated next-panel columns of the 64 rows
     const int qr = wave >> 1, qc = wave & 1;
     const bool diag_tile = isA && ib == jb;
     const int R = rowbase + 32 * qr, C = r0 + UT * jb + 32 * qc;
-    const bool wave_on = !(diag_tile && qc > qr) && R < rowlim && C < Kp;
+    const bool wave_on = !(diag_tile && qc > qr) && !(first && qr == 0 && qc == 0) && R < rowlim && C < Kp;
     if (wave_on) {
         const int kq = lane >> 4, li = lane & 15;
         bool blk[2][2];
@@ -831,7 +872,7 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const ModDesc* __restr
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
                 blk[rb][cb] = R + 16 * rb < rowlim && C + 16 * cb < Kp && !(diag_tile && qr == qc && cb > rb);
-        const bool to_lds = first && qr == 0 && qc == 0;
+        const bool to_lds = lead && qc == 0;
         double av[2][PW / 4], bv[2][PW / 4];
         double old[2][2][4];
 #pragma unroll
@@ -866,17 +907,42 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const ModDesc* __restr
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const double v = old[rb][cb][q] - acc[q];
-                    if (to_lds) s.L[16 * rb + li][16 * cb + kq + 4 * q] = v;
+                    if (to_lds) T[32 * qr + 16 * rb + li][16 * cb + kq + 4 * q] = v;
                     else if (row < rowlim) gst(W, 8u * (uint32_t)((C + 16 * cb + kq + 4 * q) * ld + row), v);
                 }
             }
         }
     }
-    if (!first) return;
+    if (!lead) return;
+    if (wave == 1) diag_update32(s, W, ld, kb, r0, lane);
     load_dref(s, d.A, ld, r0, tid);
-    factor_diag32(s, tid);                   // synchronises before reading s.L
-    store_diag32(W, ld, r0, s, tid);
-    if (tid == 0 && s.bad) status[8 * t + 5] = 1;
+    factor_diag32(s, tid);                   // synchronises before reading s.L and T
+    if (first) {
+        store_diag_block(d.Ld, r0, s, tid);
+        if (tid == 0 && s.bad) status[8 * t + 5] = 1;
+    }
+    // this tile's rows of the next panel (not the diagonal block itself): x L^T = w
+    if (tid < UT) {
+        const int row = rowbase + tid;
+        if (row < rowlim && !(first && tid < PW)) {
+            double x[PW];
+#pragma unroll
+            for (int c = 0; c < PW; ++c) x[c] = T[tid][c];
+#pragma unroll
+            for (int c = 0; c < PW; ++c) {
+                x[c] *= s.rd[c];
+#pragma unroll
+                for (int c2 = c + 1; c2 < PW; ++c2) x[c2] = fma(-x[c], s.L[c2][c], x[c2]);
+                __asm__ volatile("" ::: "memory");         // keep column c's LDS reads in this step
+            }
+#pragma unroll
+            for (int c = 0; c < PW; ++c) gst(W, 8u * (uint32_t)((r0 + c) * ld + row), x[c]);
+            if (row < Kp) {
+#pragma unroll
+                for (int c = 0; c < PW; ++c) gst(W, 8u * (uint32_t)(row * ld + r0 + c), x[c]);   // mirror
+            }
+        }
+    }
 }
 
 // D L = Z for 16 rows of D per work group: block columns of SB from the last; the product
@@ -906,14 +972,18 @@ __global__ __launch_bounds__(64 * TW) void tri_solve_rows_kernel(const ModDesc* 
     __shared__ double part[TW][2][16][17];
     __shared__ double Tt[16][SB + 1];
     const uint32_t zrow = (uint32_t)(Kp + min(rb0 + li, m - 1));     // this lane's row of D (clamped)
+    // the diagonal blocks: from the side array, or from W after the one-work-group retry
+    const bool retried = status[8 * t + 5] != 0;
     for (int J = Kp - SB; J >= 0; J -= SB) {
         double lv[NL], zv[NZ];
 #pragma unroll
         for (int u = 0; u < NL; ++u) {
             const int f = tid + u * NT, c = f / SB, r = f % SB;
-            lv[u] = f < SB * SB && r >= c ? gld(W, 8u * (uint32_t)((J + c) * ld + J + r)) : 0.0;
+            lv[u] = f < SB * SB && r >= c
+                ? (retried ? gld(W, 8u * (uint32_t)((J + c) * ld + J + r)) : d.Ld[(int64_t)J * SB + f]) : 0.0;
         }
-        const double dv = tid < SB ? gld(W, 8u * (uint32_t)((J + tid) * ld + J + tid)) : 1.0;
+        const double dv = tid < SB ? (retried ? gld(W, 8u * (uint32_t)((J + tid) * ld + J + tid))
+                                              : d.Ld[(int64_t)J * SB + tid * SB + tid]) : 1.0;
 #pragma unroll
         for (int u = 0; u < NZ; ++u) {
             const int f = tid + u * NT, r = f & 15, c = f >> 4;
@@ -1041,15 +1111,14 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
         const unsigned sg = 1 + (unsigned)std::min<int64_t>(64, std::max<int64_t>(1, (cells + 4095) / 4096));
         hipLaunchKernelGGL(chol_setup_kernel, dim3(sg, n_desc), dim3(256), 0, st, dev_desc, m, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        for (int kb = 0; kb < max_kpad; kb += PW) {
-            const unsigned pg = (unsigned)((max_kpad + m - kb - PW + 255) / 256);
-            hipLaunchKernelGGL(chol_panel_kernel, dim3(pg, n_desc), dim3(256), 0, st, dev_desc, m, status, kb);
+        // the first panel's rows; every later panel is solved by the update launch before it
+        const unsigned pg = (unsigned)((max_kpad + m - PW + 255) / 256);
+        hipLaunchKernelGGL(chol_panel_kernel, dim3(pg, n_desc), dim3(256), 0, st, dev_desc, m, status, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int kb = 0; kb + PW < max_kpad; kb += PW) {
+            hipLaunchKernelGGL(chol_update_kernel, dim3(update_tiles(max_kpad, m, kb), n_desc), dim3(256), 0, st,
+                               dev_desc, m, status, kb);
             if ((e = hipGetLastError()) != hipSuccess) return e;
-            const int nt = update_tiles(max_kpad, m, kb);
-            if (nt > 0) {
-                hipLaunchKernelGGL(chol_update_kernel, dim3(nt, n_desc), dim3(256), 0, st, dev_desc, m, status, kb);
-                if ((e = hipGetLastError()) != hipSuccess) return e;
-            }
         }
         hipLaunchKernelGGL(chol_factor_kernel, dim3(n_desc), dim3(CT), 0, st, dev_desc, m, status, 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;

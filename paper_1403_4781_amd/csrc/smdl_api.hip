@@ -425,6 +425,9 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
     plan.solver = h->mod_solver;
     double* A = (double*)h->ws((t + ".A").c_str(), abytes);
     double* W = (double*)h->ws((t + ".W").c_str(), abytes);
+    size_t ldbytes = 0;
+    for (auto& s : specs) ldbytes += (size_t)pad64(s.K) * 32 * 8;
+    double* Ld = (double*)h->ws((t + ".Ld").c_str(), ldbytes);
     plan.cnt = (int32_t*)h->ws((t + ".cnt").c_str(), (total_atoms + 1) * 4);
     plan.fill = (int32_t*)h->ws((t + ".fill").c_str(), (total_atoms + 1) * 4);
     plan.ptr = (int32_t*)h->ws((t + ".ptr").c_str(), (total_atoms + 1) * 4);
@@ -439,17 +442,18 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
     plan.arena = A;
     plan.arena_len = (int64_t)(abytes / 8);
     plan.part = plan.chunks > 1 ? (double*)h->ws((t + ".part").c_str(), abytes * (plan.chunks - 1)) : nullptr;
-    if (!A || !W || !plan.cnt || !plan.fill || !plan.ptr || !plan.list_sig || !plan.list_coef ||
+    if (!A || !W || !Ld || !plan.cnt || !plan.fill || !plan.ptr || !plan.list_sig || !plan.list_coef ||
         !plan.status || !plan.desc || (plan.chunks > 1 && !plan.part))
         return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     std::vector<ModDesc> md(specs.size());
-    size_t ao = 0;
+    size_t ao = 0, lo = 0;
     int64_t atom0 = 0;
     for (size_t i = 0; i < specs.size(); ++i) {
         const auto& s = specs[i];
         const int Kp = pad64(s.K);
-        md[i] = ModDesc{s.Y, s.idx, s.coef, s.nnz, s.n, atom0, s.D, A + ao, W + ao, s.K, Kp, s.s_stride, 0};
+        md[i] = ModDesc{s.Y, s.idx, s.coef, s.nnz, s.n, atom0, s.D, A + ao, W + ao, Ld + lo, s.K, Kp, s.s_stride, 0};
         ao += (size_t)(Kp + m) * Kp;
+        lo += (size_t)Kp * 32;
         atom0 += s.K;
     }
     plan.host_desc = md;

@@ -108,6 +108,7 @@ struct ModDesc {
     float* D;                // m x K dictionary (in/out)
     double* A;               // Kpad x Kpad FP64 workspace (products)
     double* W;               // (Kpad + m) x Kpad FP64 workspace (factorisation)
+    double* Ld;              // Kpad x 32 FP64: the factored 32 x 32 diagonal blocks (multi-work-group solve)
     int K, Kpad;
     int s_stride;            // ELL row stride
     int pad_;
