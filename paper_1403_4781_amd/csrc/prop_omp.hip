@@ -193,6 +193,8 @@ __device__ __forceinline__ void r_run(RState<SM>& st, const RCtx& x, std::intege
 template <int SM>
 __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
     __shared__ float ys[16][SMDL_MAX_M];
+    __shared__ int s_fbcnt[4];
+    __shared__ int s_fbbase;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int g = lane & (GR - 1);
@@ -264,14 +266,28 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
     }
 #pragma unroll
     for (int off = 1; off < GR; off <<= 1) rr += __shfl_xor(rr, off, 64);
+    // the signals that miss the threshold go to the fallback list: one atomic per work group (a
+    // counter taken once per signal serialises some 10^5 atomics on one address)
+    const bool miss = valid && sqrtf(rr) > a.eps_fb;
+    const uint64_t mb = __ballot(g == 0 && miss);                 // bits at the group leaders
+    const int wave = tid >> 6;
+    if (lane == 0) s_fbcnt[wave] = __popcll(mb);
+    __syncthreads();
+    if (tid == 0) {
+        int tot = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int c = s_fbcnt[w];
+            s_fbcnt[w] = tot;
+            tot += c;
+        }
+        s_fbbase = tot > 0 ? atomicAdd(a.fb_count, tot) : 0;
+    }
+    __syncthreads();
     if (!valid) return;
-    const bool miss = sqrtf(rr) > a.eps_fb;
     if (g == 0) {
         if (a.fell_back) a.fell_back[n] = miss ? 1 : 0;
-        if (miss) {
-            const int pos = atomicAdd(a.fb_count, 1);
-            a.fb_list[pos] = (int32_t)n;
-        }
+        if (miss) a.fb_list[s_fbbase + s_fbcnt[wave] + __popcll(mb & ((1ull << lane) - 1ull))] = (int32_t)n;
     }
     if (miss) return;    // the full OMP writes this signal's code
     if (g < a.s_out) {

@@ -126,6 +126,15 @@ def test_mod_unused_atoms_and_ridge(h, dev, solver):
     assert np.linalg.norm(Dn[:2] - Dref[:2], axis=1).max() <= 1e-3
 
 
+def test_mod_solver_mode_checked(h):
+    import paper_1403_4781_amd as smdl
+    print("case mod solver mode", flush=True)
+    for bad in (-1, 3):
+        with pytest.raises(smdl.SmdlError, match="E_ARG"):
+            h.set_mod_solver(bad)
+    h.set_mod_solver(0)
+
+
 def test_mod_rejects_bad_indices(h, dev):
     import paper_1403_4781_amd as smdl
     print("case mod bad index", flush=True)
