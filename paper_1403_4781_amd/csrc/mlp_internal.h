@@ -61,7 +61,7 @@ struct WgArgs {
     int t_off;                // ... plus this: the step number t of the bias corrections
 };
 
-// The whole network on R batch rows per work group (R = 16 or 32; every width a multiple of
+// The whole network on R batch rows per work group (R = 16, 32 or 64; every width a multiple of
 // 32, the input width m a multiple of 4 and at most SMDL_MAX_M): y / ||y|| -> hidden layers ->
 // output layer, every activation kept in LDS as BF16.  Inference (logits set): FP32 logits of
 // the valid rows.  Training (tmask set): the BCE deltas of the output layer, then the deltas of
@@ -89,9 +89,10 @@ struct RowsArgs {
 };
 
 // Rows per work group of the fused network kernel for these widths, 0 when the activations of
-// 16 rows do not fit in LDS or a width is unsupported.  Inference takes 32 rows where they fit
-// (half the weight reads per row over many work groups); a training batch takes 16 (twice the
-// work groups on the chip, half the serial matrix work in each).
+// 16 rows do not fit in LDS or a width is unsupported.  Inference keeps only two activation
+// buffers and takes 64 rows where they fit, else 32 (fewer weight reads per row over many work
+// groups); a training batch keeps every layer's activations and takes 16 (twice the work groups on
+// the chip, half the serial matrix work in each).
 int mlp_rows_per_block(int n_layers, const int* widths, bool train);
 hipError_t launch_mlp_rows(const RowsArgs& a, int R, hipStream_t st);
 

@@ -16,6 +16,8 @@
 // needs (through LDS), and a per-row-block column sum of its FP32 output (bias gradients).
 // The output layer's epilogue applies the BCE loss to a multi-hot label bitmask.  One grouped
 // launch forms every weight gradient and applies Adam (FP32 masters and moments, BF16 W and W^T).
+#include <algorithm>
+
 #include "mlp_internal.h"
 
 namespace {
@@ -517,9 +519,14 @@ __global__ __launch_bounds__(rows_threads<R>()) void mlp_rows_kernel(RowsArgs g)
     const int r16 = lane & 15, kq = lane >> 4;
     const int L = g.n_layers;
     const int64_t r0 = (int64_t)blockIdx.x * R;
-    const bool train = g.tmask != nullptr;
-    // LDS rows of the input of layer l (l = L: the output deltas)
+    const bool train = R == 16 && g.tmask != nullptr;    // only the 16-row form trains
+    // LDS rows of the input of layer l (l = L: the output deltas).  Training keeps every layer's
+    // activations (the backward pass reads them); inference needs only the input and the output of
+    // the current layer and alternates between two buffers.
+    int wmax = 0;
+    for (int i = 0; i < L; ++i) wmax = max(wmax, g.w[i]);
     auto buf = [&](int l) -> uint16_t* {
+        if (!train) return act + (l & 1) * (R * (wmax + ACT_PAD));
         int off = 0;
         for (int i = 0; i < l; ++i) off += R * (g.w[i] + ACT_PAD);
         return act + off;
@@ -688,8 +695,13 @@ __global__ __launch_bounds__(rows_threads<R>()) void mlp_rows_kernel(RowsArgs g)
     }
 }
 
-size_t rows_lds_bytes(int n_layers, const int* w, int R) {
+size_t rows_lds_bytes(int n_layers, const int* w, int R, bool train) {
     size_t b = 0;
+    if (!train) {
+        int wmax = 0;
+        for (int l = 0; l < n_layers; ++l) wmax = std::max(wmax, w[l]);
+        return (size_t)2 * R * 2 * (wmax + ACT_PAD);
+    }
     for (int l = 0; l <= n_layers; ++l) b += (size_t)R * 2 * (w[l] + ACT_PAD);
     return b;
 }
@@ -742,30 +754,38 @@ int mlp_rows_per_block(int n_layers, const int* widths, bool train) {
     for (int l = 0; l <= n_layers; ++l)
         if (widths[l] < 32 || widths[l] % 32) return 0;
     const size_t budget = SMDL_LDS_BYTES - 1024;    // the static arrays
-    if (!train && rows_lds_bytes(n_layers, widths, 32) <= budget) return 32;
-    if (rows_lds_bytes(n_layers, widths, 16) <= budget) return 16;
+    if (!train && rows_lds_bytes(n_layers, widths, 64, false) <= budget) return 64;
+    if (!train && rows_lds_bytes(n_layers, widths, 32, false) <= budget) return 32;
+    if (rows_lds_bytes(n_layers, widths, 16, train) <= budget) return 16;
     return 0;
 }
 
 hipError_t launch_mlp_rows(const RowsArgs& a, int R, hipStream_t st) {
-    if ((R != 16 && R != 32) || a.Bpad < R || a.Bpad % R || a.B > a.Bpad) return hipErrorInvalidValue;
-    const size_t budget = SMDL_LDS_BYTES - 1024;
-    if (mlp_rows_per_block(a.n_layers, a.w, false) == 0 || rows_lds_bytes(a.n_layers, a.w, R) > budget)
+    const bool train = a.tmask != nullptr;
+    if ((R != 16 && R != 32 && R != 64) || (train && R != 16) || a.Bpad < R || a.Bpad % R || a.B > a.Bpad)
         return hipErrorInvalidValue;
-    if (a.tmask ? (!a.loss || a.tstride < (a.w[a.n_layers] + 31) / 32) : !a.logits) return hipErrorInvalidValue;
-    const size_t lds = rows_lds_bytes(a.n_layers, a.w, R);
-    static bool attr_set = false;   // both instantiations may use the whole LDS budget
+    const size_t budget = SMDL_LDS_BYTES - 1024;
+    if (mlp_rows_per_block(a.n_layers, a.w, false) == 0 || rows_lds_bytes(a.n_layers, a.w, R, train) > budget)
+        return hipErrorInvalidValue;
+    if (train ? (!a.loss || a.tstride < (a.w[a.n_layers] + 31) / 32) : !a.logits) return hipErrorInvalidValue;
+    const size_t lds = rows_lds_bytes(a.n_layers, a.w, R, train);
+    static bool attr_set = false;   // every instantiation may use the whole LDS budget
     if (!attr_set) {
         const int full = (int)(SMDL_LDS_BYTES - 1024);
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_rows_kernel<32>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_rows_kernel<64>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, full);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_rows_kernel<32>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, full);
         if (e == hipSuccess)
             e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_rows_kernel<16>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, full);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    if (R == 32)
+    if (R == 64)
+        hipLaunchKernelGGL(mlp_rows_kernel<64>, dim3((unsigned)(a.Bpad / 64)), dim3(rows_threads<64>()), lds, st, a);
+    else if (R == 32)
         hipLaunchKernelGGL(mlp_rows_kernel<32>, dim3((unsigned)(a.Bpad / 32)), dim3(rows_threads<32>()), lds, st, a);
     else
         hipLaunchKernelGGL(mlp_rows_kernel<16>, dim3((unsigned)(a.Bpad / 16)), dim3(rows_threads<16>()), lds, st, a);
