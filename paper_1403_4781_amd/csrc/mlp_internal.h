@@ -110,6 +110,8 @@ hipError_t launch_to_bf16(const float* w, int64_t n, int cols, int rows, uint16_
 // Proposer-restricted OMP.
 struct RestrictedArgs {
     const float* D;          // m x K
+    const float4* dfrag;     // the packed dictionary fragments of the plain OMP kernel (alpha0)
+    int mchunks;             // 64-row chunks of m
     const float* gram;       // Kpad rows of gld floats
     int gld;
     int Kpad, m, K;

@@ -561,6 +561,8 @@ extern "C" smdl_status smdl_omp_code_proposed(smdl_t h, smdl_prop_t p, const flo
     if ((e = launch_zero_i32(fb_cnt, 1, h->stream)) != hipSuccess) return h->hip(e, "zero");
     RestrictedArgs r{};
     r.D = D;
+    r.dfrag = sets[0].frag;
+    r.mchunks = plan.mchunks;
     r.gram = sets[0].gram;
     r.gld = sets[0].gld;
     r.Kpad = sets[0].Kpad;

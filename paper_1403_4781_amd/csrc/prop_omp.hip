@@ -195,6 +195,7 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
     __shared__ float ys[16][SMDL_MAX_M];
     __shared__ int s_fbcnt[4];
     __shared__ int s_fbbase;
+    extern __shared__ float alpha[];                    // 16 x (Kpad + 4): alpha0 of the signals
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int g = lane & (GR - 1);
@@ -203,7 +204,45 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
     const bool valid = n < a.N;
     const int m = a.m;
     const int nc = a.n_cand;
-    for (int i = g; i < m; i += GR) ys[slot][i] = valid ? a.Y[n * m + i] : 0.f;
+    const int mpad = 64 * a.mchunks;
+    for (int i = g; i < mpad; i += GR) ys[slot][i] = valid && i < m ? a.Y[n * m + i] : 0.f;
+    __syncthreads();
+    // alpha0 = D^T y of the 16 signals on the matrix cores from the packed fragments, in the order
+    // of the plain OMP kernel (so the same bits); each lane then reads its candidates' entries
+    const int Kpad = a.Kpad, astride = Kpad + 4;
+    {
+        const int i16 = lane & 15, kq = lane >> 4, wave = tid >> 6;
+        const int NRB = Kpad >> 4, rbw = NRB >> 2, rb0 = wave * rbw;
+        float4 yv[SMDL_MAX_M / 64][4];
+#pragma unroll
+        for (int c = 0; c < SMDL_MAX_M / 64; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                yv[c][q] = c < a.mchunks ? *reinterpret_cast<const float4*>(&ys[i16][64 * c + 16 * kq + 4 * q])
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int rb = 0; rb < rbw; ++rb) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < SMDL_MAX_M / 64; ++c) {
+                if (c < a.mchunks) {
+                    const float4* fp = a.dfrag + ((size_t)(c * NRB + rb0 + rb) * 4) * 64 + lane;
+                    float4 af[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) af[q] = fp[q * 64];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q].x, yv[c][q].x, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q].y, yv[c][q].y, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q].z, yv[c][q].z, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q].w, yv[c][q].w, acc, 0, 0, 0);
+                    }
+                }
+            }
+            // tile entry (atom 16 rb + 4 kq + q, signal i16) in lane i16 + 16 kq, register q
+            *reinterpret_cast<float4*>(&alpha[i16 * astride + 16 * (rb0 + rb) + 4 * kq]) =
+                make_float4(acc[0], acc[1], acc[2], acc[3]);
+        }
+    }
     __syncthreads();
     int cid[EC];
     RState<SM> st;
@@ -211,29 +250,12 @@ __global__ __launch_bounds__(256) void restricted_omp_kernel(RestrictedArgs a) {
     for (int i = g; i < m; i += GR) ysq = fmaf(ys[slot][i], ys[slot][i], ysq);
 #pragma unroll
     for (int off = 1; off < GR; off <<= 1) ysq += __shfl_xor(ysq, off, 64);
-    const bool vec = (m & 3) == 0 && (reinterpret_cast<uintptr_t>(a.D) & 15) == 0;
 #pragma unroll
     for (int t = 0; t < EC; ++t) {
         const int e = g + GR * t;
         cid[t] = (valid && e < nc) ? a.cand[n * nc + e] : -1;
         if (cid[t] < 0 || cid[t] >= a.K) cid[t] = -1;
-        float acc = 0.f;
-        if (cid[t] >= 0) {
-            const float* d = a.D + (int64_t)cid[t] * m;
-            int i = 0;
-            if (vec) {
-                for (; i < m; i += 4) {
-                    const float4 dv = *reinterpret_cast<const float4*>(d + i);
-                    const float4 yv = *reinterpret_cast<const float4*>(&ys[slot][i]);
-                    acc = fmaf(dv.x, yv.x, acc);
-                    acc = fmaf(dv.y, yv.y, acc);
-                    acc = fmaf(dv.z, yv.z, acc);
-                    acc = fmaf(dv.w, yv.w, acc);
-                }
-            }
-            for (; i < m; ++i) acc = fmaf(d[i], ys[slot][i], acc);
-        }
-        st.c[t] = acc;
+        st.c[t] = cid[t] >= 0 ? alpha[slot * astride + cid[t]] : 0.f;
     }
 #pragma unroll
     for (int i = 0; i < SM; ++i) {
@@ -317,9 +339,23 @@ hipError_t launch_topk(const float* logits, int64_t N, int K, int n_cand, int32_
 }
 
 hipError_t launch_restricted_omp(const RestrictedArgs& a, hipStream_t st) {
+    if (a.Kpad % 64 || a.Kpad > SMDL_MAX_K || a.mchunks < 1 || a.mchunks > SMDL_MAX_M / 64 || !a.dfrag)
+        return hipErrorInvalidValue;
+    const size_t lds = (size_t)16 * (a.Kpad + 4) * 4;    // alpha0 of the 16 signals
+    static bool attr_set = false;
+    if (!attr_set) {
+        const int full = 16 * (SMDL_MAX_K + 4) * 4;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&restricted_omp_kernel<8>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, full);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&restricted_omp_kernel<SMDL_MAX_S>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, full);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
     if (a.s <= 8)
-        hipLaunchKernelGGL(restricted_omp_kernel<8>, dim3((unsigned)((a.N + 15) / 16)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(restricted_omp_kernel<8>, dim3((unsigned)((a.N + 15) / 16)), dim3(256), lds, st, a);
     else
-        hipLaunchKernelGGL(restricted_omp_kernel<SMDL_MAX_S>, dim3((unsigned)((a.N + 15) / 16)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(restricted_omp_kernel<SMDL_MAX_S>, dim3((unsigned)((a.N + 15) / 16)), dim3(256), lds, st, a);
     return hipGetLastError();
 }
