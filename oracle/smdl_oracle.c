@@ -531,11 +531,14 @@ int ora_mlp_grad(int n_layers, const int* widths, const double* const* W,
                 for (int i = 0; i < in; ++i) g[i] += dr * h[i];
             }
             if (l > 0) {
+                /* dh[i] = sum over o (in increasing order) of bf16(W[o][i]) bf16(delta[o]),
+                 * accumulated row by row of W */
                 const double* zprev = zs + zoff - in;   /* z_l of the previous layer */
-                for (int i = 0; i < in; ++i) {
-                    double s = 0.0;
-                    for (int o = 0; o < out; ++o) s += ora_bf16(W[l][(size_t)o * in + i]) * ora_bf16(delta[o]);
-                    dh[i] = s;
+                for (int i = 0; i < in; ++i) dh[i] = 0.0;
+                for (int o = 0; o < out; ++o) {
+                    const double dr = ora_bf16(delta[o]);
+                    const double* w = W[l] + (size_t)o * in;
+                    for (int i = 0; i < in; ++i) dh[i] += ora_bf16(w[i]) * dr;
                 }
                 for (int i = 0; i < in; ++i) delta[i] = zprev[i] > 0.0 ? dh[i] : 0.0;
             }
