@@ -160,6 +160,19 @@ def run_large(args, smdl, synth, torch, dev):
     h = smdl.Handle(0)
     widths = [256, 1024, 1024, 1024]
     Ws, bs = synth.mlp_init(widths)
+    if args.train_only:
+        D = torch.from_numpy(synth.gaussian_dictionary(np.random.default_rng(1), w.m, w.K).astype(np.float32)).to(dev)
+        labels = h.omp_code(D, Yt, 16)
+        prop = h.proposer(Ws, bs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = prop.train(Yt, labels, epochs=args.train_only, batch=1024, lr=1e-3, shuffle_seed=1)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        prop.close()
+        print(json.dumps({"train_only": args.train_only, "widths": widths, "ms": ms,
+                          "steps": args.train_only * (Ytr.shape[0] // 1024), "losses": losses}))
+        return
 
     def step():
         info = {}
@@ -428,7 +441,8 @@ def main():
     ap.add_argument("--omp-tile", default="",
                     help="with --omp-only: 'lanes,signals_per_item' to force that OMP tile")
     ap.add_argument("--train-only", type=int, default=0,
-                    help="only train the proposer this many epochs on the 200000 training pairs (for profilers)")
+                    help="only train the proposer this many epochs on the 200000 training pairs (for profilers; "
+                         "the default and the large configuration)")
     ap.add_argument("--trials", type=int, default=20, help="e1: independent trials")
     ap.add_argument("--e1-iters", type=int, default=100, help="e1: iterations of every learning stage")
     ap.add_argument("--e1-oracle-trials", type=int, default=1, help="e1: trials also run by the FP64 oracle")

@@ -8,17 +8,18 @@
 // row block then column block, lane l = (n % 16) + 16 ((k % 32) / 8) of a block holding the 8
 // consecutive entries of row n from k - k % 8.  N % 16 == 0, K % 32 == 0.
 //
-// C[M x N] = A[M x K] B[N x K]^T (BF16, FP32 accumulation; A row-major, B in fragment order) with
-// a fused epilogue, applied in this order: + bias[col]; BCE (when tmask is set: the value is the
+// C[M x N] = A[M x K] B[N x K]^T (BF16, FP32 accumulation; A and B in fragment order) with a
+// fused epilogue, applied in this order: + bias[col]; BCE (when tmask is set: the value is the
 // logit z of batch row `row`, target bit col of tmask[rows[row]], replaced by (sigmoid(z) - t) *
-// scale, loss terms added to *loss); ReLU; ReLU-backward mask (zero where mask <= 0); zero for
-// rows >= Mvalid.  Then the value is stored as FP32 (rows < Mvalid only) and/or BF16 [M x N]
-// (ld = ldo), BF16 transposed [N x M] in fragment order, and summed per column over each 32-row
-// block into colpart[M / 32][N].  M, N and K multiples of 32, lda a multiple of 8.
+// scale, loss terms added to *loss); ReLU; ReLU-backward mask (zero where mask <= 0; mask is
+// [M x ldmask] in fragment order, ldmask = N); zero for rows >= Mvalid.  Then the value is
+// stored as FP32 row-major (ld = ldo, rows < Mvalid only) and/or BF16 [M x N] in fragment order
+// (ldo = N), BF16 transposed [N x M] in fragment order, and summed per column over each 32-row
+// block into colpart[M / 32][N].  M, N and K multiples of 32.  Products with at least 256 tiles
+// of 64 x 64 (M and N multiples of 64) take 64 x 64 tiles, the others 32 x 32.
 struct NtArgs {
     const uint16_t* A;
     const uint16_t* B;
-    int lda;
     int M, N, K;
     int Mvalid;
     const float* bias;
@@ -88,8 +89,9 @@ struct RowsArgs {
     float* colpart[4];          // [Bpad / R x w[l+1]]
 };
 
-// Rows per work group of the fused network kernel for these widths, 0 when the activations of
-// 16 rows do not fit in LDS or a width is unsupported.  Inference keeps only two activation
+// Rows per work group of the fused network kernel for these widths, 0 (the per-layer path) when
+// the activations of 16 rows do not fit in LDS, a width is unsupported, or, for a training
+// batch, the network has at least 3 * 2^18 weights.  Inference keeps only two activation
 // buffers and takes 64 rows where they fit, else 32 (fewer weight reads per row over many work
 // groups); a training batch keeps every layer's activations and takes 16 (twice the work groups on
 // the chip, half the serial matrix work in each).

@@ -3,12 +3,12 @@
 // Every product of the forward and backward passes is one "NT" GEMM, C[M x N] = A[M x K] B[N x K]^T
 // with both operands stored with the reduction dimension contiguous, on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Fragments are loaded straight from global
-// memory (16 bytes per lane); the four waves of a block split the reduction of one 32 x 32
-// output tile, each issuing the loads of four k-steps at once, and sum their partials in LDS.
-// The BF16 weights and the transposed activations and deltas are stored in fragment order (see
-// pk_off), so that the 64 lanes of a fragment load read one contiguous kilobyte; in row-major
-// order the 16 lanes of a k-group would touch 16 different rows, and the vector L1 cache would
-// serve the load one lane at a time.  The layouts that make every product NT:
+// memory (16 bytes per lane); the waves of a block split the reduction of one 32 x 32 or
+// 64 x 64 output tile and sum their partials in LDS.  Every BF16 matrix in global memory
+// (weights, activations, deltas and their transposes) is stored in fragment order (see pk_off),
+// so that the 64 lanes of a fragment load read one contiguous kilobyte; in row-major order the
+// 16 lanes of a k-group would touch 16 different rows, and the vector L1 cache would serve the
+// load one lane at a time.  The layouts that make every product NT:
 //   forward   h_l   [B x w_l]   = h_{l-1} [B x w_{l-1}] . W_l [w_l x w_{l-1}]^T
 //   backward  d_{l-1} [B x w_{l-1}] = d_l [B x w_l] . W_l^T [w_{l-1} x w_l]^T   (ReLU mask)
 //   weights   dW_l [w_l x w_{l-1}] = d_l^T [w_l x B] . h_{l-1}^T [w_{l-1} x B]^T
@@ -48,26 +48,15 @@ __device__ __forceinline__ const uint16_t* pk_frag(const uint16_t* base, int nb,
 
 // Partial 32 x 32 tile (m0, n0) of A B^T over the k-steps (32 wide) wave, wave + NW, ...:
 // 2 x 2 blocks of 16 x 16; the loads of up to four k-steps are issued before their MFMAs.
-// A is row-major (ld lda; rows >= M read clamped, their results discarded) or, with A_PK, in
-// fragment order; B is in fragment order (N % 32 == 0).
-template <bool A_PK, int NW>
-__device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int lda, int M,
-                                           const uint16_t* __restrict__ B, int K,
+// A and B are in fragment order (K columns).
+template <int NW>
+__device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B, int K,
                                            int m0, int n0, int wave, int lane, f32x4 (&acc)[2][2]) {
-    const int r16 = lane & 15, kq = lane >> 4;
     const uint16_t* ap[2];
     const uint16_t* bp[2];
-    int astep;
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-        if (A_PK) {
-            ap[f] = pk_frag(A, (m0 >> 4) + f, K, lane);
-            astep = 512;
-        } else {
-            const int r = min(m0 + 16 * f + r16, M - 1);
-            ap[f] = A + (int64_t)r * lda + 8 * kq;
-            astep = 32;
-        }
+        ap[f] = pk_frag(A, (m0 >> 4) + f, K, lane);
         bp[f] = pk_frag(B, (n0 >> 4) + f, K, lane);
     }
 #pragma unroll
@@ -82,7 +71,7 @@ __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int l
             const int st = min(s0 + NW * c, nsteps - 1);
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
-                a[c][f] = *reinterpret_cast<const bf16x8*>(ap[f] + (int64_t)astep * st);
+                a[c][f] = *reinterpret_cast<const bf16x8*>(ap[f] + (int64_t)512 * st);
                 b[c][f] = *reinterpret_cast<const bf16x8*>(bp[f] + (int64_t)512 * st);
             }
         }
@@ -100,13 +89,12 @@ __device__ __forceinline__ void nt_partial(const uint16_t* __restrict__ A, int l
 
 // The full 32 x 32 tile: the NW waves' partials summed through LDS into tile[r][c] (the first
 // 256 threads form the sums).
-template <bool A_PK, int NW>
-__device__ __forceinline__ void nt_tile(const uint16_t* __restrict__ A, int lda, int M,
-                                        const uint16_t* __restrict__ B, int K,
+template <int NW>
+__device__ __forceinline__ void nt_tile(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B, int K,
                                         int m0, int n0, float (*part)[TILE][RP], float (*tile)[RP]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     f32x4 acc[2][2];
-    nt_partial<A_PK, NW>(A, lda, M, B, K, m0, n0, wave, lane, acc);
+    nt_partial<NW>(A, B, K, m0, n0, wave, lane, acc);
     // D[i][j] of a 16 x 16 block sits in lane j + 16 (i / 4), register i % 4
     const int r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -129,7 +117,7 @@ __device__ __forceinline__ void nt_tile(const uint16_t* __restrict__ A, int lda,
     __syncthreads();
 }
 
-// C = A B^T with the fused epilogue (see NtArgs).  Grid: (ceil(N / 32), M / 32); M % 32 == 0.
+// C = A B^T with the fused epilogue (see NtArgs) on 32 x 32 tiles.  Grid: (N / 32, M / 32).
 // Thread t finishes row t / 8, columns 4 (t % 8) .. + 3 of the tile.
 __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
     __shared__ float part[4][TILE][RP];
@@ -146,13 +134,13 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
     float4 bias4 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (g.bias && full) bias4 = *reinterpret_cast<const float4*>(g.bias + n0 + cl0);
     uint2 mask4 = make_uint2(0x3f803f80u, 0x3f803f80u);      // bf16 ones
-    if (g.mask && full) mask4 = *reinterpret_cast<const uint2*>(g.mask + (int64_t)row * g.ldmask + n0 + cl0);
+    if (g.mask && full) mask4 = *reinterpret_cast<const uint2*>(g.mask + pk_off(row, n0 + cl0, g.ldmask));
     uint32_t tbits = 0;
     if (g.tmask && rv && full) {
         const int src = g.rows ? g.rows[row] : row;
         tbits = g.tmask[(int64_t)src * g.tstride + ((n0 + cl0) >> 5)] >> ((n0 + cl0) & 31);
     }
-    nt_tile<false, 4>(g.A, g.lda, g.M, g.B, g.K, m0, n0, part, tile);
+    nt_tile<4>(g.A, g.B, g.K, m0, n0, part, tile);
 
     double lsum = 0.0;
     float v[4];
@@ -184,7 +172,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
         if (g.out_bf16) {
             const uint32_t lo = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
             const uint32_t hi = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-            *reinterpret_cast<uint2*>(g.out_bf16 + (int64_t)row * g.ldo + n0 + cl0) = make_uint2(lo, hi);
+            *reinterpret_cast<uint2*>(g.out_bf16 + pk_off(row, n0 + cl0, g.ldo)) = make_uint2(lo, hi);
         }
     }
     if (g.outT) {
@@ -226,6 +214,205 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
     }
 }
 
+
+// 64 x 64 tiles, for products with at least one tile per CU: each operand row is read once per
+// 64 output columns instead of 32.  Each of the four waves forms the whole tile (4 x 4 blocks
+// of 16 x 16) over a quarter of the reduction; the four partial tiles are summed through LDS.
+constexpr int T64 = 64;
+constexpr int P64 = T64 + 1;
+constexpr int NT64_MIN_TILES = 256;   // one tile per CU
+__device__ __forceinline__ void nt64_load(const uint16_t* ab, const uint16_t* bb, int64_t rstride, int s,
+                                          int nsteps, bf16x8 (&a)[2][4], bf16x8 (&b)[2][4]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int64_t off = (int64_t)512 * min(s + 4 * c, nsteps - 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a[c][i] = *reinterpret_cast<const bf16x8*>(ab + i * rstride + off);
+            b[c][i] = *reinterpret_cast<const bf16x8*>(bb + i * rstride + off);
+        }
+    }
+}
+__device__ __forceinline__ void nt64_mma(const bf16x8 (&a)[2][4], const bf16x8 (&b)[2][4], int s, int nsteps,
+                                         f32x4 (&acc)[4][4]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (s + 4 * c >= nsteps) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c][i], b[c][j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Wave `wave`'s partial 64 x 64 tile (m0, n0) of A B^T (both in fragment order, K columns) over
+// the k-steps wave, wave + 4, ..., stored in part[wave].  A set is two of the wave's k-steps; the
+// loads of the next set are in flight while the current one is multiplied, and the loads inside
+// the loop are unconditional, so the waits before the MFMAs cover exactly the set they multiply.
+__device__ __forceinline__ void nt64_partials(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
+                                              int K, int m0, int n0, int wave, int lane,
+                                              float (*part)[T64][P64]) {
+    const int nsteps = K >> 5;
+    const int64_t rstride = (int64_t)nsteps * 512;      // elements between 16-row blocks
+    const uint16_t* ab = pk_frag(A, m0 >> 4, K, lane);
+    const uint16_t* bb = pk_frag(B, n0 >> 4, K, lane);
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 a0[2][4], b0[2][4], a1[2][4], b1[2][4];
+    int s = wave;
+    int sets = wave < nsteps ? ((nsteps - wave + 3) / 4 + 1) / 2 : 0;
+    nt64_load(ab, bb, rstride, s, nsteps, a0, b0);
+    for (; sets > 2; sets -= 2, s += 16) {
+        nt64_load(ab, bb, rstride, s + 8, nsteps, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);   // keep each set's loads ahead of the other's MFMAs
+        nt64_mma(a0, b0, s, nsteps, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        nt64_load(ab, bb, rstride, s + 16, nsteps, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        nt64_mma(a1, b1, s + 8, nsteps, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (sets == 2) {
+        nt64_load(ab, bb, rstride, s + 8, nsteps, a1, b1);
+        nt64_mma(a0, b0, s, nsteps, acc);
+        nt64_mma(a1, b1, s + 8, nsteps, acc);
+    } else if (sets == 1) {
+        nt64_mma(a0, b0, s, nsteps, acc);
+    }
+    // D[i][j] of a 16 x 16 block sits in lane j + 16 (i / 4), register i % 4
+    const int r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) part[wave][16 * i + 4 * kq + q][16 * j + r16] = acc[i][j][q];
+}
+
+// C = A B^T with the fused epilogue (see NtArgs) on 64 x 64 tiles.  Grid: (N / 64, M / 64).
+// Thread t finishes row t / 4, columns 16 (t % 4) .. + 15 of the tile.
+__global__ __launch_bounds__(256) void gemm_nt64_kernel(NtArgs g) {
+    __shared__ float part[4][T64][P64];
+    __shared__ uint16_t tT[T64][T64 + 8];
+    __shared__ double lred[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar loop control
+    const int m0 = blockIdx.y * T64, n0 = blockIdx.x * T64;
+    // the epilogue's operands are requested before the product
+    const int rl = tid >> 2, cl0 = (tid & 3) * 16;
+    const int row = m0 + rl;
+    const bool rv = row < g.Mvalid;
+    float bias[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float4 b4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (g.bias) b4 = *reinterpret_cast<const float4*>(g.bias + n0 + cl0 + 4 * q);
+        bias[4 * q] = b4.x;
+        bias[4 * q + 1] = b4.y;
+        bias[4 * q + 2] = b4.z;
+        bias[4 * q + 3] = b4.w;
+    }
+    uint4 mk[2] = {make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u),
+                   make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u)};   // bf16 ones
+    if (g.mask) {
+        mk[0] = *reinterpret_cast<const uint4*>(g.mask + pk_off(row, n0 + cl0, g.ldmask));
+        mk[1] = *reinterpret_cast<const uint4*>(g.mask + pk_off(row, n0 + cl0 + 8, g.ldmask));
+    }
+    uint32_t tbits = 0;
+    if (g.tmask && rv) {
+        const int src = g.rows ? g.rows[row] : row;
+        tbits = g.tmask[(int64_t)src * g.tstride + ((n0 + cl0) >> 5)] >> ((n0 + cl0) & 31);
+    }
+
+    nt64_partials(g.A, g.B, g.K, m0, n0, wave, lane, part);
+    __syncthreads();
+
+    double lsum = 0.0;
+    float v[16];
+    const uint32_t mw[8] = {mk[0].x, mk[0].y, mk[0].z, mk[0].w, mk[1].x, mk[1].y, mk[1].z, mk[1].w};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int c = cl0 + e;
+        float x = ((part[0][rl][c] + part[1][rl][c]) + (part[2][rl][c] + part[3][rl][c])) + bias[e];
+        if (g.tmask) {
+            // BCE with logits: loss max(z,0) - t z + log(1 + e^-|z|), delta (sigmoid(z) - t) s
+            if (rv) {
+                const float t = (float)((tbits >> e) & 1u);
+                const float sg = 1.0f / (1.0f + expf(-x));
+                lsum += (double)(fmaxf(x, 0.f) - t * x + log1pf(expf(-fabsf(x))));
+                x = (sg - t) * g.scale;
+            } else {
+                x = 0.f;
+            }
+        }
+        if (g.relu) x = fmaxf(x, 0.f);
+        if (!(bf2f((uint16_t)(mw[e >> 1] >> (16 * (e & 1)))) > 0.f)) x = 0.f;
+        if (!rv) x = 0.f;
+        v[e] = x;
+    }
+    if (g.out_f32 && rv) {   // may be the caller's rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<float4*>(g.out_f32 + (int64_t)row * g.ldo + n0 + cl0 + 4 * q) =
+                make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    }
+    if (g.out_bf16) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                w[q] = (uint32_t)f2bf(v[8 * h + 2 * q]) | ((uint32_t)f2bf(v[8 * h + 2 * q + 1]) << 16);
+            *reinterpret_cast<uint4*>(g.out_bf16 + pk_off(row, n0 + cl0 + 8 * h, g.ldo)) =
+                make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+    if (g.outT) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tT[cl0 + e][rl] = f2bf(v[e]);
+    }
+    if (g.tmask) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+        if (lane == 0) lred[wave] = lsum;
+    }
+    if (g.colpart) {
+        // every thread has read its own entries of the partial tiles; part[0] now takes the values
+#pragma unroll
+        for (int e = 0; e < 16; ++e) part[0][rl][cl0 + e] = v[e];
+    }
+    __syncthreads();
+    if (g.colpart) {
+        // column c: thread (c, q) sums rows 16 q .. 16 q + 15, then the two sums of each 32-row
+        // half are added
+        const int c = tid & 63, q = tid >> 6;
+        float cs = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; r += 4)
+            cs += (part[0][16 * q + r][c] + part[0][16 * q + r + 1][c]) +
+                  (part[0][16 * q + r + 2][c] + part[0][16 * q + r + 3][c]);
+        part[1][q][c] = cs;
+        __syncthreads();
+        if (tid < 2 * T64) {
+            const int hh = tid >> 6;
+            g.colpart[(int64_t)((m0 >> 5) + hh) * g.N + n0 + c] = part[1][2 * hh][c] + part[1][2 * hh + 1][c];
+        }
+    }
+    if (g.tmask && tid == 0) atomicAdd(g.loss, (lred[0] + lred[1]) + (lred[2] + lred[3]));
+    if (g.outT) {
+        // thread t: column t / 4 of the tile, rows 16 (t % 4) .. + 15 -> 32 bytes of out^T
+        // ([N x M] in fragment order)
+        const int c = tid >> 2, r0 = (tid & 3) * 16;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            *reinterpret_cast<uint4*>(g.outT + pk_off(n0 + c, m0 + r0 + 8 * h, g.M)) =
+                *reinterpret_cast<const uint4*>(&tT[c][r0 + 8 * h]);
+    }
+}
 
 // Weight gradients of every layer in one launch: blocks [tile0_l, tile0_l + tiles_l) form
 // 32 x 32 tiles of dW_l = d_l^T h_{l-1}; the blocks after them form the bias gradients from
@@ -295,7 +482,7 @@ __global__ __launch_bounds__(64 * NW) void wgrad_kernel(WgArgs g) {
         v4 = *reinterpret_cast<const float4*>(L.vW + idx);
         w4 = *reinterpret_cast<const float4*>(L.W + idx);
     }
-    nt_tile<true, NW>(L.dT, 0, L.wo, L.hT, g.Bpad, m0, n0, part, tile);
+    nt_tile<NW>(L.dT, L.hT, g.Bpad, m0, n0, part, tile);
     if (!g.adam) {
         if (ok)
             *reinterpret_cast<float4*>(L.dW_out + idx) =
@@ -331,25 +518,28 @@ __global__ __launch_bounds__(64 * NW) void wgrad_kernel(WgArgs g) {
 }
 
 // h0 = bf16(y / ||y||) for the batch rows (gathered through `rows`), as [Bpad x m] and, when
-// h0T is set, [m x Bpad]; rows >= B are zero.  Block = 64 batch rows, four lanes per row (each
-// m / 4 consecutive entries), staged through LDS for the transposed copy.
-constexpr int PREP_ROWS = 64;
-__global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ Y, int64_t B, int m, int64_t Bpad,
-                                                   const int32_t* __restrict__ rows, uint16_t* __restrict__ h0,
-                                                   uint16_t* __restrict__ h0T) {
+// h0T is set, [m x Bpad], both in fragment order; rows >= B are zero.  Block = 16 batch rows,
+// eight lanes per row (each m / 8 consecutive entries, a multiple of 4), staged through LDS for
+// the transposed copy; Bpad / 16 blocks, so that a batch of a thousand rows spreads over 64 CUs.
+constexpr int PREP_ROWS = 16;
+constexpr int PREP_LANES = 8;
+__global__ __launch_bounds__(PREP_ROWS * PREP_LANES) void prep_kernel(const float* __restrict__ Y, int64_t B, int m,
+                                                                    int64_t Bpad, const int32_t* __restrict__ rows,
+                                                                    uint16_t* __restrict__ h0,
+                                                                    uint16_t* __restrict__ h0T) {
     __shared__ uint16_t t[PREP_ROWS][SMDL_MAX_M + 2];
     const int tid = threadIdx.x;
-    const int rr = tid >> 2, part = tid & 3;
+    const int rr = tid / PREP_LANES, part = tid % PREP_LANES;
     const int64_t b = (int64_t)blockIdx.x * PREP_ROWS + rr;
-    const int seg = m / 4;                       // m % 32 == 0
+    const int seg = m / PREP_LANES;              // m % 32 == 0
     const int i0 = part * seg;
-    float y[SMDL_MAX_M / 4];
+    float y[SMDL_MAX_M / PREP_LANES];
     float ss = 0.f;
     const bool valid = b < B;
     const int64_t src = valid ? (rows ? rows[b] : b) : 0;
     const bool vec = (reinterpret_cast<uintptr_t>(Y) & 15) == 0;
 #pragma unroll
-    for (int q = 0; q < SMDL_MAX_M / 16; ++q) {
+    for (int q = 0; q < SMDL_MAX_M / (4 * PREP_LANES); ++q) {
         if (4 * q < seg) {
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             const float* yp = Y + src * m + i0 + 4 * q;
@@ -361,11 +551,11 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ Y, 
             ss = fmaf(v.x, v.x, fmaf(v.y, v.y, fmaf(v.z, v.z, fmaf(v.w, v.w, ss))));
         }
     }
-    ss += __shfl_xor(ss, 1, 64);
-    ss += __shfl_xor(ss, 2, 64);
+#pragma unroll
+    for (int off = 1; off < PREP_LANES; off <<= 1) ss += __shfl_xor(ss, off, 64);
     const float inv = ss > 0.f ? 1.0f / sqrtf(ss) : 0.f;
 #pragma unroll
-    for (int q = 0; q < SMDL_MAX_M / 16; ++q) {
+    for (int q = 0; q < SMDL_MAX_M / (4 * PREP_LANES); ++q) {
         if (4 * q < seg) {
             uint16_t hv[4];
 #pragma unroll
@@ -373,15 +563,14 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ Y, 
                 hv[e] = valid ? f2bf(y[4 * q + e] * inv) : (uint16_t)0;
                 t[rr][i0 + 4 * q + e] = hv[e];
             }
-            if (b < Bpad)
-                *reinterpret_cast<uint2*>(h0 + b * m + i0 + 4 * q) =
-                    make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16), (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
+            *reinterpret_cast<uint2*>(h0 + pk_off((int)b, i0 + 4 * q, m)) =
+                make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16), (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
         }
     }
     if (!h0T) return;
     __syncthreads();
-    // h0^T ([m x Bpad] in fragment order): thread t writes rows 4 (t % 16) .. + 3 of column t / 16
-    for (int q = tid; q < m * (PREP_ROWS / 4); q += 256) {
+    // h0^T ([m x Bpad] in fragment order): item q writes rows 4 (q % 4) .. + 3 of column q / 4
+    for (int q = tid; q < m * (PREP_ROWS / 4); q += PREP_ROWS * PREP_LANES) {
         const int i = q / (PREP_ROWS / 4), rc = (q % (PREP_ROWS / 4)) * 4;
         const uint32_t lo = (uint32_t)t[rc][i] | ((uint32_t)t[rc + 1][i] << 16);
         const uint32_t hi = (uint32_t)t[rc + 2][i] | ((uint32_t)t[rc + 3][i] << 16);
@@ -748,12 +937,21 @@ inline int grid_n(int64_t n) {
 
 }  // namespace
 
+// A training batch of a network with at least this many weights takes the per-layer path: the
+// fused kernel streams every weight once per 16 rows, the per-layer products once per 64.
+constexpr int64_t TRAIN_PER_LAYER_WEIGHTS = 3 << 18;
+
 int mlp_rows_per_block(int n_layers, const int* widths, bool train) {
     if (n_layers < 1 || n_layers > 4) return 0;
     if (widths[0] > SMDL_MAX_M) return 0;
     for (int l = 0; l <= n_layers; ++l)
         if (widths[l] < 32 || widths[l] % 32) return 0;
     const size_t budget = SMDL_LDS_BYTES - 1024;    // the static arrays
+    if (train) {
+        int64_t weights = 0;
+        for (int l = 0; l < n_layers; ++l) weights += (int64_t)widths[l] * widths[l + 1];
+        if (weights >= TRAIN_PER_LAYER_WEIGHTS) return 0;
+    }
     if (!train && rows_lds_bytes(n_layers, widths, 64, false) <= budget) return 64;
     if (!train && rows_lds_bytes(n_layers, widths, 32, false) <= budget) return 32;
     if (rows_lds_bytes(n_layers, widths, 16, train) <= budget) return 16;
@@ -793,8 +991,11 @@ hipError_t launch_mlp_rows(const RowsArgs& a, int R, hipStream_t st) {
 }
 
 hipError_t launch_gemm_nt(const NtArgs& g, hipStream_t st) {
-    if (g.M % TILE || g.K % 32 || g.N < TILE || g.N % TILE || g.M < TILE || g.lda % 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gemm_nt_kernel, dim3((g.N + TILE - 1) / TILE, g.M / TILE), dim3(256), 0, st, g);
+    if (g.M % TILE || g.K % 32 || g.N < TILE || g.N % TILE || g.M < TILE) return hipErrorInvalidValue;
+    if (g.M % T64 == 0 && g.N % T64 == 0 && (int64_t)(g.M / T64) * (g.N / T64) >= NT64_MIN_TILES)
+        hipLaunchKernelGGL(gemm_nt64_kernel, dim3(g.N / T64, g.M / T64), dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL(gemm_nt_kernel, dim3(g.N / TILE, g.M / TILE), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
@@ -821,7 +1022,8 @@ hipError_t launch_wgrad(WgArgs& g, hipStream_t st) {
 hipError_t launch_prep(const float* Y, int64_t B, int m, int64_t Bpad, const int32_t* rows, uint16_t* h0,
                        uint16_t* h0T, hipStream_t st) {
     if (m > SMDL_MAX_M || m % 32 || Bpad % PREP_ROWS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)(Bpad / PREP_ROWS)), dim3(256), 0, st, Y, B, m, Bpad, rows, h0, h0T);
+    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)(Bpad / PREP_ROWS)), dim3(PREP_ROWS * PREP_LANES), 0, st, Y, B, m,
+                       Bpad, rows, h0, h0T);
     return hipGetLastError();
 }
 

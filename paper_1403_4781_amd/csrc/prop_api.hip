@@ -36,17 +36,18 @@ namespace {
 
 inline int64_t pad64b(int64_t x) { return (x + 63) / 64 * 64; }
 
-// Activation buffers for a batch of Bpad rows (a multiple of 64).  With R > 0 the fused
-// network kernel runs R rows per work group and keeps the row-major activations and deltas in
-// LDS, so only the transposed copies, the column sums and the logits live here.
+// Activation buffers for a batch of Bpad rows (a multiple of 64), every BF16 matrix in fragment
+// order.  With R > 0 the fused network kernel runs R rows per work group and keeps the
+// activations and deltas in LDS, so only the transposed copies, the column sums and the logits
+// live here; with R = 0 (the per-layer path) the activations and deltas live here too.
 struct Acts {
     int64_t Bpad = 0;
     int R = 0;
-    std::vector<uint16_t*> h;      // h[l]: Bpad x widths[l], input of layer l (BF16)
-    float* logits = nullptr;       // Bpad x K (inference)
+    std::vector<uint16_t*> h;      // h[l]: Bpad x widths[l], input of layer l
+    float* logits = nullptr;       // Bpad x K (inference, FP32 row-major)
     // training only
     std::vector<uint16_t*> hT;     // widths[l] x Bpad
-    std::vector<uint16_t*> d;      // d[l]: Bpad x widths[l + 1], BF16 delta at the output of layer l
+    std::vector<uint16_t*> d;      // d[l]: Bpad x widths[l + 1], delta at the output of layer l
     std::vector<uint16_t*> dT;     // widths[l + 1] x Bpad
     std::vector<float*> part;      // (Bpad / 32) x widths[l + 1] column sums of the FP32 deltas
 };
@@ -98,7 +99,6 @@ hipError_t enqueue_forward(smdl_t h, smdl_prop_t p, const float* Y, int64_t B, c
         const int wi = p->widths[l], wo = p->widths[l + 1];
         NtArgs g{};
         g.A = a.h[l];
-        g.lda = wi;
         g.B = p->Wpk[l];
         g.M = (int)Bpad;
         g.N = wo;
@@ -138,7 +138,6 @@ hipError_t enqueue_deltas(smdl_t h, smdl_prop_t p, int64_t B, Acts& a) {
         const int wi = p->widths[l], wo = p->widths[l + 1];
         NtArgs g{};
         g.A = a.d[l];
-        g.lda = wo;
         g.B = p->WTpk[l];
         g.M = (int)Bpad;
         g.N = wi;

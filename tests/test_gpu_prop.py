@@ -95,6 +95,57 @@ def test_wide_network_per_layer_path(h, dev):
     p.close()
 
 
+def test_wide_network_large_batch_logits(h, dev):
+    """Per-layer products with at least 256 tiles of 64 x 64 take the 64 x 64 kernel: the
+    inference forward of 64-4096-1024 on 1000 signals (bias, ReLU, fragment-order BF16 hidden
+    activations, FP32 logits; a ragged last row tile)."""
+    rng = np.random.default_rng(23)
+    Y = rng.standard_normal((1000, 64)).astype(np.float32)
+    print("case 64-4096-1024 logits, 1000 signals", flush=True)
+    Ws, bs = synth.mlp_init([64, 4096, 1024], seed=21)
+    p = h.proposer(Ws, bs)
+    lg = p.logits(_t(Y, dev)).cpu().numpy()
+    e = _relfro(lg, oracle.mlp_forward(Ws, bs, Y))
+    print(f"  logits rel {e:.2e}", flush=True)
+    assert e <= REL
+    p.close()
+
+
+def test_per_layer_training_large_batch(h, dev):
+    """64-1024-1024 (over a million weights) trains layer by layer; on 1000 signals every
+    product and the weight gradients take the 64 x 64 kernels (BCE output layer, ReLU masks,
+    transposed copies, column sums).  Gradients against the oracle, then one Adam step against
+    the oracle's Adam applied to the oracle's gradients."""
+    widths = [64, 1024, 1024]
+    Ws, bs = synth.mlp_init(widths, seed=24)
+    rng = np.random.default_rng(25)
+    Y = rng.standard_normal((1000, 64)).astype(np.float32)
+    idx = np.stack([rng.choice(1024, 8, replace=False) for _ in range(1000)]).astype(np.int32)
+    labels = oracle.Codes(idx, np.ones((1000, 8)), np.full(1000, 8, np.int32))
+    print("case 64-1024-1024 gradients, 1000 signals", flush=True)
+    p = h.proposer(Ws, bs)
+    loss, dW, db = p.grad(_t(Y, dev), _codes_t(labels, dev))
+    lref, dWr, dbr = oracle.mlp_grad(Ws, bs, Y, oracle.multi_hot(labels, 1024))
+    print(f"  loss gpu {loss:.6f} oracle {lref:.6f}", flush=True)
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    for l in range(2):
+        ew, eb = _relfro(dW[l].cpu().numpy(), dWr[l]), _relfro(db[l].cpu().numpy(), dbr[l])
+        print(f"  layer {l}: dW rel {ew:.2e} db rel {eb:.2e}", flush=True)
+        assert ew <= REL and eb <= REL
+    print("case 64-1024-1024 Adam step", flush=True)
+    p.train(_t(Y, dev), _codes_t(labels, dev), epochs=1, batch=1000, lr=1e-3)
+    W1, b1 = p.weights()
+    for l in range(2):
+        for gpu, w0, g in ((W1[l], Ws[l], dWr[l]), (b1[l], bs[l], dbr[l])):
+            w = w0.astype(np.float64).ravel().copy()
+            mom, vel = np.zeros_like(w), np.zeros_like(w)
+            oracle.adam(w, g.ravel().copy(), mom, vel, 1, lr=1e-3)
+            e = _relfro(gpu.astype(np.float64).ravel() - w0.astype(np.float64).ravel(), w - w0.astype(np.float64).ravel())
+            print(f"  layer {l} update rel {e:.2e}", flush=True)
+            assert e <= 0.05     # Adam's first step is ~lr*sign(g): a tiny |g| may flip sign
+    p.close()
+
+
 def test_training_step_and_loss_decrease(h, dev):
     widths = [64, 128, 96, 256]
     Ws, bs = synth.mlp_init(widths, seed=13)
