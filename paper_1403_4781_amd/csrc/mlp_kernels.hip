@@ -667,15 +667,53 @@ __device__ __forceinline__ void rows_tile(const uint16_t* __restrict__ A, int ld
     }
 }
 
-// Stores the FP32 deltas v of a tile (row 16 i + 4 kq + q, column n0 + 16 j + r16 of the lane):
-// BF16 into LDS (when O is set), BF16 transposed into dT ([w x Bpad] in fragment order) and the column sums over
-// the R rows into colpart[block][w].
+// acc = rows 0 .. R - 1 of A (LDS, ld lda) times weight rows n0 .. n0 + 15 of Bw (fragment order)
+// over K, eight k-steps of B fragments per round trip (the registers of four k-steps of a
+// 32-column tile): for a layer with fewer 32-column tiles than waves, 16-column tiles occupy
+// twice the waves and halve each wave's chain of dependent loads.
 template <int RB>
-__device__ __forceinline__ void store_deltas(const float (&v)[RB][2][4], uint16_t* O, int ldo, uint16_t* dT,
+__device__ __forceinline__ void rows_tile16(const uint16_t* __restrict__ A, int lda, const uint16_t* __restrict__ Bw,
+                                            int K, int n0, int lane, f32x4 (&acc)[RB]) {
+    const int r16 = lane & 15, kq = lane >> 4;
+    const uint16_t* bp = pk_frag(Bw, n0 >> 4, K, lane);
+    const uint16_t* ap = A + r16 * lda + 8 * kq;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = K >> 5;
+    for (int s0 = 0; s0 < nsteps; s0 += 8) {
+        bf16x8 b[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) b[c] = *reinterpret_cast<const bf16x8*>(bp + 512 * min(s0 + c, nsteps - 1));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bf16x8 a[4][RB];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int st = min(s0 + 4 * h + c, nsteps - 1);
+#pragma unroll
+                for (int i = 0; i < RB; ++i) a[c][i] = *reinterpret_cast<const bf16x8*>(ap + i * 16 * lda + 32 * st);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (s0 + 4 * h + c < nsteps) {
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c][i], b[4 * h + c], acc[i], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// Stores the FP32 deltas v of a tile of NB 16-column blocks (row 16 i + 4 kq + q, column
+// n0 + 16 j + r16 of the lane): BF16 into LDS (when O is set), BF16 transposed into dT
+// ([w x Bpad] in fragment order) and the column sums over the R rows into colpart[block][w].
+template <int RB, int NB = 2>
+__device__ __forceinline__ void store_deltas(const float (&v)[RB][NB][4], uint16_t* O, int ldo, uint16_t* dT,
                                              int64_t Bpad, int64_t r0, float* colpart, int w, int n0, int lane) {
     const int r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NB; ++j) {
         const int col = n0 + 16 * j + r16;
         float cs = 0.f;
 #pragma unroll
@@ -781,6 +819,35 @@ __global__ __launch_bounds__(rows_threads<R>()) void mlp_rows_kernel(RowsArgs g)
         const uint16_t* A = buf(l);
         uint16_t* O = buf(l + 1);
         const int lda = wi + ACT_PAD, ldo = wo + ACT_PAD;
+        if (train && last && 2 * (wo / 32) <= FT / 64) {
+            // an output layer with at most half as many 32-column tiles as waves: 16-column tiles
+            for (int ct = wave; ct < wo / 16; ct += FT / 64) {
+                const int n0 = 16 * ct;
+                const float bj = g.bias[l][n0 + r16];
+                f32x4 acc[RB];
+                rows_tile16<RB>(A, lda, g.W[l], wi, n0, lane, acc);
+                float v[RB][1][4];
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int src = s_src[16 * i + 4 * kq + q];
+                        const uint32_t word = src >= 0 ? g.tmask[(int64_t)src * g.tstride + (n0 >> 5)] : 0u;
+                        float x = 0.f;
+                        if (src >= 0) {
+                            const float z = acc[i][q] + bj;
+                            const float t = (float)((word >> ((n0 & 31) + r16)) & 1u);
+                            const float sg = 1.0f / (1.0f + expf(-z));
+                            lsum += (double)(fmaxf(z, 0.f) - t * z + log1pf(expf(-fabsf(z))));
+                            x = (sg - t) * g.scale;
+                        }
+                        v[i][0][q] = x;
+                    }
+                store_deltas<RB, 1>(v, L > 1 ? O : nullptr, ldo, g.dT[l], g.Bpad, r0, g.colpart[l], wo, n0, lane);
+            }
+            __syncthreads();
+            continue;
+        }
         for (int ct = wave; ct < wo / 32; ct += FT / 64) {
             const int n0 = 32 * ct;
             const float bj[2] = {g.bias[l][n0 + r16], g.bias[l][n0 + 16 + r16]};
