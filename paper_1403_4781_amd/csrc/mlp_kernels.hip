@@ -1059,6 +1059,8 @@ hipError_t launch_mlp_rows(const RowsArgs& a, int R, hipStream_t st) {
 
 hipError_t launch_gemm_nt(const NtArgs& g, hipStream_t st) {
     if (g.M % TILE || g.K % 32 || g.N < TILE || g.N % TILE || g.M < TILE) return hipErrorInvalidValue;
+    // fragment-order mask and BF16 output rows are N wide
+    if ((g.mask && g.ldmask != g.N) || (g.out_bf16 && g.ldo != g.N)) return hipErrorInvalidValue;
     if (g.M % T64 == 0 && g.N % T64 == 0 && (int64_t)(g.M / T64) * (g.N / T64) >= NT64_MIN_TILES)
         hipLaunchKernelGGL(gemm_nt64_kernel, dim3(g.N / T64, g.M / T64), dim3(256), 0, st, g);
     else
