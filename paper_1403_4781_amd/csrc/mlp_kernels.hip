@@ -30,6 +30,16 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// BCE with logits for logit z and target t: returns sigmoid(z) - t and adds the loss term
+// max(z, 0) - t z + log(1 + e^-|z|) to loss.  One exponential e = e^-|z| in (0, 1] serves both:
+// sigmoid(z) = 1 / (1 + e) for z >= 0 and e / (1 + e) otherwise.
+__device__ __forceinline__ float bce_delta(float z, float t, double& loss) {
+    const float e = __expf(-fabsf(z));
+    const float r = __fdividef(1.0f, 1.0f + e);
+    loss += (double)(fmaxf(z, 0.f) - t * z + __logf(1.0f + e));
+    return (z >= 0.f ? r : e * r) - t;
+}
+
 constexpr int TILE = 32;       // output tile of a block (rows and columns)
 constexpr int RP = TILE + 1;   // LDS row of an FP32 tile
 
@@ -154,9 +164,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
             // BCE with logits: loss max(z,0) - t z + log(1 + e^-|z|), delta (sigmoid(z) - t) s
             if (rv && cv) {
                 const float t = (float)((tbits >> e) & 1u);
-                const float sg = 1.0f / (1.0f + expf(-x));
-                lsum += (double)(fmaxf(x, 0.f) - t * x + log1pf(expf(-fabsf(x))));
-                x = (sg - t) * g.scale;
+                x = bce_delta(x, t, lsum) * g.scale;
             } else {
                 x = 0.f;
             }
@@ -342,9 +350,7 @@ __global__ __launch_bounds__(256) void gemm_nt64_kernel(NtArgs g) {
             // BCE with logits: loss max(z,0) - t z + log(1 + e^-|z|), delta (sigmoid(z) - t) s
             if (rv) {
                 const float t = (float)((tbits >> e) & 1u);
-                const float sg = 1.0f / (1.0f + expf(-x));
-                lsum += (double)(fmaxf(x, 0.f) - t * x + log1pf(expf(-fabsf(x))));
-                x = (sg - t) * g.scale;
+                x = bce_delta(x, t, lsum) * g.scale;
             } else {
                 x = 0.f;
             }
@@ -837,9 +843,7 @@ __global__ __launch_bounds__(rows_threads<R>()) void mlp_rows_kernel(RowsArgs g)
                         if (src >= 0) {
                             const float z = acc[i][q] + bj;
                             const float t = (float)((word >> ((n0 & 31) + r16)) & 1u);
-                            const float sg = 1.0f / (1.0f + expf(-z));
-                            lsum += (double)(fmaxf(z, 0.f) - t * z + log1pf(expf(-fabsf(z))));
-                            x = (sg - t) * g.scale;
+                            x = bce_delta(z, t, lsum) * g.scale;
                         }
                         v[i][0][q] = x;
                     }
@@ -900,9 +904,7 @@ __global__ __launch_bounds__(rows_threads<R>()) void mlp_rows_kernel(RowsArgs g)
                             if (src >= 0) {
                                 const float z = acc[i][j][q] + bj[j];
                                 const float t = (float)((word >> (16 * j + r16)) & 1u);
-                                const float sg = 1.0f / (1.0f + expf(-z));
-                                lsum += (double)(fmaxf(z, 0.f) - t * z + log1pf(expf(-fabsf(z))));
-                                x = (sg - t) * g.scale;
+                                x = bce_delta(z, t, lsum) * g.scale;
                             }
                             v[i][j][q] = x;
                         }
