@@ -22,12 +22,8 @@
 
 namespace {
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
-    u += 0x7fffu + ((u >> 16) & 1u);                                      // round to nearest even
-    return (uint16_t)(u >> 16);
-}
+// FP32 -> BF16, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // BCE with logits for logit z and target t: returns sigmoid(z) - t and adds the loss term
