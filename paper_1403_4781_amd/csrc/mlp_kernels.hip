@@ -123,7 +123,8 @@ __device__ __forceinline__ void nt_tile(const uint16_t* __restrict__ A, const ui
     __syncthreads();
 }
 
-// C = A B^T with the fused epilogue (see NtArgs) on 32 x 32 tiles.  Grid: (N / 32, M / 32).
+// C = A B^T with the fused epilogue (see NtArgs) on 32 x 32 tiles.  Grid: (M / 32, N / 32): row
+// tiles on x, which allows up to 2^31 - 1 of them.
 // Thread t finishes row t / 8, columns 4 (t % 8) .. + 3 of the tile.
 __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
     __shared__ float part[4][TILE][RP];
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
     __shared__ uint16_t tT[TILE][TILE + 2];
     __shared__ double lred[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+    const int m0 = blockIdx.x * TILE, n0 = blockIdx.y * TILE;
     // the epilogue's operands (bias, ReLU mask, label bits) are requested before the product
     const int rl = tid >> 3, cl0 = (tid & 7) * 4;
     const int row = m0 + rl;
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtArgs g) {
             float cs = 0.f;
 #pragma unroll
             for (int r = 0; r < 8; ++r) cs += part[0][r][tid];
-            g.colpart[(int64_t)blockIdx.y * g.N + n0 + tid] = cs;
+            g.colpart[(int64_t)blockIdx.x * g.N + n0 + tid] = cs;
         }
     }
     if (g.tmask && tid == 0) atomicAdd(g.loss, (lred[0] + lred[1]) + (lred[2] + lred[3]));
@@ -297,7 +298,7 @@ __device__ __forceinline__ void nt64_partials(const uint16_t* __restrict__ A, co
             for (int q = 0; q < 4; ++q) part[wave][16 * i + 4 * kq + q][16 * j + r16] = acc[i][j][q];
 }
 
-// C = A B^T with the fused epilogue (see NtArgs) on 64 x 64 tiles.  Grid: (N / 64, M / 64).
+// C = A B^T with the fused epilogue (see NtArgs) on 64 x 64 tiles.  Grid: (M / 64, N / 64).
 // Thread t finishes row t / 4, columns 16 (t % 4) .. + 15 of the tile.
 __global__ __launch_bounds__(256) void gemm_nt64_kernel(NtArgs g) {
     __shared__ float part[4][T64][P64];
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) void gemm_nt64_kernel(NtArgs g) {
     __shared__ double lred[4];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar loop control
-    const int m0 = blockIdx.y * T64, n0 = blockIdx.x * T64;
+    const int m0 = blockIdx.x * T64, n0 = blockIdx.y * T64;
     // the epilogue's operands are requested before the product
     const int rl = tid >> 2, cl0 = (tid & 3) * 16;
     const int row = m0 + rl;
@@ -1060,9 +1061,9 @@ hipError_t launch_gemm_nt(const NtArgs& g, hipStream_t st) {
     // fragment-order mask and BF16 output rows are N wide
     if ((g.mask && g.ldmask != g.N) || (g.out_bf16 && g.ldo != g.N)) return hipErrorInvalidValue;
     if (g.M % T64 == 0 && g.N % T64 == 0 && (int64_t)(g.M / T64) * (g.N / T64) >= NT64_MIN_TILES)
-        hipLaunchKernelGGL(gemm_nt64_kernel, dim3(g.N / T64, g.M / T64), dim3(256), 0, st, g);
+        hipLaunchKernelGGL(gemm_nt64_kernel, dim3(g.M / T64, g.N / T64), dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL(gemm_nt_kernel, dim3(g.N / TILE, g.M / TILE), dim3(256), 0, st, g);
+        hipLaunchKernelGGL(gemm_nt_kernel, dim3(g.M / TILE, g.N / TILE), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
