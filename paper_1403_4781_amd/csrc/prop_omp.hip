@@ -19,10 +19,10 @@ constexpr int EC = MAXC / GR;   // candidate entries per lane
 
 // Top-n_cand selection, 16 lanes per signal (4 signals per wave); lane g holds the logits of
 // atoms g + 16 t (t < E).  Logits become order-preserving 32-bit keys (NaN ranks last); a
-// bisection over the key bits finds the n_cand-th largest key T (32 rounds of one group
-// count); the keys above T are taken, and of the keys equal to T the lowest atoms.  As atom
-// 16 t + g orders like (t, g), every lane writes its chosen atoms straight to their positions
-// in increasing atom order (group ballots and popcounts).
+// bisection over the key bits finds a threshold T (at most 32 rounds of one group count); the
+// keys above T are taken, and of the keys equal to T the lowest atoms.  As atom 16 t + g
+// orders like (t, g), every lane writes its chosen atoms straight to their positions in
+// increasing atom order (group ballots and popcounts).
 // NaN ranks below every number (key 1); key 0 marks padding entries, which are never chosen
 // because at least K >= n_cand keys are >= 1.
 __device__ __forceinline__ uint32_t order_key(float x) {
@@ -58,14 +58,23 @@ __global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ log
         const int k = g + 16 * t;
         key[t] = (valid && k < K) ? order_key(logits[n * K + k]) : 0u;   // 0: never chosen
     }
-    // T = the largest threshold with at least n_cand keys >= T
+    // T = the largest threshold with at least n_cand keys >= T.  A group stops as soon as exactly
+    // n_cand keys are >= T: those keys are then the selection whatever the remaining bits (T lies
+    // above the next key and at most at the n_cand-th, so no key equal to the n_cand-th is left
+    // out), and the steps below take all of them.  The wave stops when its four groups have.
     uint32_t T = 0u;
+    bool done = false;
     for (int b = 31; b >= 0; --b) {
         const uint32_t T2 = T | (1u << b);
         int c = 0;
 #pragma unroll
         for (int t = 0; t < E; ++t) c += key[t] >= T2 ? 1 : 0;
-        T = group_isum(c) >= n_cand ? T2 : T;
+        const int cs = group_isum(c);
+        if (!done && cs >= n_cand) {
+            T = T2;
+            done = cs == n_cand;
+        }
+        if (__ballot(!done) == 0) break;
     }
     int gt = 0;
 #pragma unroll
