@@ -51,9 +51,10 @@ def lib():
                                 C.c_double, dp, ip, dp, ip]
         L.ora_split_merge.argtypes = [dp, C.c_int, C.c_int64, i64p, C.c_int, i64p, ip, ip, C.c_int,
                                       C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
-                                      dp, ip, dp, ip, dp, dp]
+                                      dp, ip, dp, ip, dp, dp, i64p]
         L.ora_set_bf16.argtypes = [C.c_int]
         L.ora_threads.restype = C.c_int
+        L.ora_set_threads.argtypes = [C.c_int]
         L.ora_bf16.argtypes = [C.c_double]
         L.ora_bf16.restype = C.c_double
         L.ora_mlp_forward.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(dp), C.POINTER(dp), dp,
@@ -145,9 +146,39 @@ def learn(Y, K, s, iters, tau=TAU, dep_tol=DEP_TOL, codes=True):
     return D, (Codes(idx, coef, nnz) if codes else None)
 
 
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int):
+    """The splitmix64 generator (Steele, Lea and Flood, OOPSLA 2014), from its published
+    definition: the state advances by the golden-ratio increment 0x9E3779B97F4A7C15 and each
+    output is the state passed through the variant-13 finaliser (xor-shift 30, multiply
+    0xBF58476D1CE4E5B9, xor-shift 27, multiply 0x94D049BB133111EB, xor-shift 31)."""
+    state = seed & _MASK64
+    while True:
+        state = (state + 0x9E3779B97F4A7C15) & _MASK64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        yield z ^ (z >> 31)
+
+
+def seeded_permutation(n: int, seed: int) -> np.ndarray:
+    """0..n-1 shuffled by Fisher-Yates from the last position down, position i exchanged with
+    position (next splitmix64 output) mod (i + 1)."""
+    p = list(range(n))
+    g = splitmix64(seed)
+    for i in range(n - 1, 0, -1):
+        j = next(g) % (i + 1)
+        p[i], p[j] = p[j], p[i]
+    return np.asarray(p, np.int64)
+
+
 def split_merge(Y, perm, offsets, K_local, s_local, K, iters_local, iters_merge, s_merge, s_final,
-                tau=TAU, dep_tol=DEP_TOL, codes=True):
-    """Algorithm 1 end to end.  Returns (D, codes, D_local (sumK, m), scales (L,))."""
+                tau=TAU, dep_tol=DEP_TOL, codes=True, merge_seed=0):
+    """Algorithm 1 end to end.  Returns (D, codes, D_local (sumK, m), scales (L,)).  With a
+    nonzero merge_seed the merge learns on the pooled columns in the order of
+    seeded_permutation(sum K_local, merge_seed), so that it starts from its first K of them."""
     Y = _d(Y)
     N, m = Y.shape
     perm = np.ascontiguousarray(perm, np.int64)
@@ -165,7 +196,9 @@ def split_merge(Y, perm, offsets, K_local, s_local, K, iters_local, iters_merge,
                                _p(K_local, C.c_int32), _p(s_local, C.c_int32), K, iters_local,
                                iters_merge, s_merge, s_final, tau, dep_tol, _p(D, C.c_double),
                                _p(idx, C.c_int32), _p(coef, C.c_double), _p(nnz, C.c_int32),
-                               _p(Dl, C.c_double), _p(sc, C.c_double))
+                               _p(Dl, C.c_double), _p(sc, C.c_double),
+                               _p(mp, C.c_int64) if (mp := (seeded_permutation(int(K_local.sum()), merge_seed)
+                                                            if merge_seed else None)) is not None else None)
     if rc != 0:
         raise FloatingPointError(f"oracle split-merge failed ({rc})")
     return D, (Codes(idx, coef, nnz) if codes else None), Dl, sc
@@ -174,6 +207,11 @@ def split_merge(Y, perm, offsets, K_local, s_local, K, iters_local, iters_merge,
 def threads() -> int:
     """OpenMP threads the oracle's loops run on."""
     return int(lib().ora_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's loops on n threads (for timing)."""
+    lib().ora_set_threads(int(n))
 
 
 def set_bf16_rounding(enabled: bool) -> None:
@@ -316,12 +354,13 @@ def denoise(img, D, p: int, eps: float, s_max: int):
 def tie_mask(codes: Codes, eps: float = 0.0, margin: float = 1e-5, tau: float = TAU,
              dep_tol: float = DEP_TOL) -> np.ndarray:
     """Signals whose FP64 trace comes close to a decision boundary (excluded from
-    support comparisons): a correlation near-tie (relative top-2 gap < margin), a best
-    correlation within a factor 2 of the tau stop, a dependence ratio within a factor 5
-    of dep_tol, or (error-constrained form) a residual within margin*||y|| of eps."""
+    support comparisons): a correlation near-tie (relative top-2 gap < margin) at a step that
+    goes on to pick an atom (best correlation above tau: below it the loop stops whatever the
+    gap), a best correlation within a factor 2 of the tau stop, a dependence ratio within a
+    factor 5 of dep_tol, or (error-constrained form) a residual within margin*||y|| of eps."""
     gap, cmax, l2, rn = codes.gap, codes.cmax, codes.l2, codes.rn
     with np.errstate(invalid="ignore"):
-        t = np.nan_to_num(gap < margin, nan=False).any(axis=1)
+        t = np.nan_to_num((gap < margin) & (cmax > tau), nan=False).any(axis=1)
         t |= np.nan_to_num((cmax > 0.5 * tau) & (cmax < 2 * tau), nan=False).any(axis=1)
         t |= np.nan_to_num((l2 > 0.2 * dep_tol) & (l2 < 5 * dep_tol), nan=False).any(axis=1)
         if eps > 0:
