@@ -49,7 +49,7 @@ typedef enum {
     SMDL_E_NOMEM = -4,        /* device allocation failed                                    */
     SMDL_E_HIP = -5,          /* a HIP runtime call failed (message names it)                */
     SMDL_E_NUMERIC = -6,      /* FP64 Cholesky of the MOD normal equations failed after the
-                                 ridge retry                                                 */
+                                 ridge retry, or (SMDL_CHECK_FINITE) a non-finite input      */
     SMDL_E_STATE = -7         /* handle or proposer in an unusable state                     */
 } smdl_status;
 
@@ -143,18 +143,36 @@ typedef struct {
 #define SMDL_NO_GRAPH 2u            /* do not capture/replay the iteration as a HIP graph    */
 #define SMDL_COMPOSE_CODES 4u       /* X_out = the Proposition 1 composition Z X1 (see below)
                                        instead of a fresh OMP of all N signals               */
+#define SMDL_DETERMINISTIC 8u       /* MOD products accumulated in a fixed order (per-atom lists
+                                       in signal order, each column of X X^T summed by one
+                                       thread), so that repeated runs give the same bits      */
+#define SMDL_CHECK_FINITE 16u       /* reject non-finite signals with SMDL_E_NUMERIC before any
+                                       other work                                            */
 
 typedef struct {
     int iters_local;   /* alternations on every subset (step 2)                               */
     int iters_merge;   /* alternations of the merge (step 3)                                  */
     int s_merge;       /* sparsity of the merge (step 3, s2)                                  */
     int s_final;       /* sparsity of the final coding of all N signals                       */
-    uint32_t flags;    /* SMDL_PER_SUBSET_LAUNCH | SMDL_NO_GRAPH | SMDL_COMPOSE_CODES          */
+    uint32_t flags;    /* SMDL_PER_SUBSET_LAUNCH | SMDL_NO_GRAPH | SMDL_COMPOSE_CODES |
+                          SMDL_DETERMINISTIC | SMDL_CHECK_FINITE                               */
     const float* D_local_init;  /* device m x max_t K_local[t], or NULL: subset t starts from the
                                    first K_local[t] columns of this matrix (unit-normalised) instead
                                    of its first K_local[t] signals                               */
     const float* D_merge_init;  /* device m x K, or NULL: the merge starts from this dictionary
                                    (unit-normalised) instead of the first K pooled columns       */
+    uint64_t merge_seed;        /* 0: the merge starts from the first K pooled columns (subset
+                                   order).  Otherwise from the first K columns of a random
+                                   permutation of the pooled columns: Fisher-Yates from the last
+                                   position down, position i swapped with position
+                                   (splitmix64 draw) mod (i + 1), splitmix64 seeded with this
+                                   value (Steele, Lea, Flood 2014: state += 0x9E3779B97F4A7C15,
+                                   then the variant-13 finaliser).  Ignored with D_merge_init.  */
+    smdl_codes X_local;         /* optional (idx == NULL: not wanted): receives the final local
+                                   codes X^(t) of step 2 (the codes of the returned local
+                                   dictionaries), N rows in split order (row offsets[t] + i is
+                                   signal i of subset t), local atom ids; X_local.s_max must be
+                                   >= max_t s_local[t] and <= 16                              */
 } smdl_learn_opts;
 
 /*
@@ -297,6 +315,14 @@ smdl_status smdl_set_tile(smdl_t h, int K, int s_max, int lanes_per_signal, int 
  * the same dictionaries up to rounding.  SMDL_E_ARG for another mode.
  */
 smdl_status smdl_set_mod_solver(smdl_t h, int mode);
+/*
+ * Options of every later call on the handle: SMDL_DETERMINISTIC (MOD products in a fixed order,
+ * for smdl_mod_update, smdl_learn* and smdl_split_merge_learn) and SMDL_CHECK_FINITE (the input
+ * signals, and for smdl_omp_code the dictionary, are checked first; a NaN or infinity returns
+ * SMDL_E_NUMERIC and nothing else runs).  0 clears both.  SMDL_E_ARG for any other bit.
+ * smdl_split_merge_learn uses these bits OR-ed with smdl_learn_opts.flags.
+ */
+smdl_status smdl_set_flags(smdl_t h, uint32_t flags);
 /* Enable (default) or disable automatic tuning on the first learning call of a shape. */
 smdl_status smdl_set_autotune(smdl_t h, int enabled);
 /* Wall time (ms) of the last smdl_split_merge_learn: local phase, merge phase, final coding. */

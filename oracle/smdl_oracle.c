@@ -372,7 +372,7 @@ int ora_split_merge(const double* Y, int m, int64_t N, const int64_t* perm, int 
                     const int64_t* offsets, const int32_t* K_t, const int32_t* s_t, int K,
                     int iters_local, int iters_merge, int s_merge, int s_final, double tau,
                     double dep_tol, double* D_out, int32_t* idx, double* coef, int32_t* nnz,
-                    double* D_local_out, double* scales_out) {
+                    double* D_local_out, double* scales_out, const int64_t* merge_perm) {
     if (!Y || !perm || !offsets || !K_t || !s_t || !D_out || L < 1 || offsets[L] != N) return ORA_E_ARG;
     int64_t sumK = 0;
     for (int t = 0; t < L; ++t) sumK += K_t[t];
@@ -401,6 +401,17 @@ int ora_split_merge(const double* Y, int m, int64_t N, const int64_t* perm, int 
         }
         col += K_t[t];
         free(Ys); free(ix); free(cf); free(nz);
+    }
+    /* step 3: the merge learns on the pooled columns, in the order merge_perm gives them when
+       one is passed (its initial dictionary is then its first K columns in that order) */
+    if (status == ORA_OK && merge_perm) {
+        double* Yq = (double*)malloc(sizeof(double) * (size_t)m * sumK);
+        for (int64_t i = 0; i < sumK; ++i) {
+            if (merge_perm[i] < 0 || merge_perm[i] >= sumK) { status = ORA_E_ARG; break; }
+            memcpy(Yq + (size_t)i * m, Yt + (size_t)merge_perm[i] * m, sizeof(double) * m);
+        }
+        free(Yt);
+        Yt = Yq;
     }
     if (status == ORA_OK)
         status = ora_learn(Yt, m, sumK, K, s_merge, iters_merge, tau, dep_tol, D_out, NULL, NULL, NULL);
@@ -631,5 +642,14 @@ int ora_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Set the number of threads of the OpenMP loops (timing on one thread or all cores). */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

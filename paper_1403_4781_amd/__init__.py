@@ -26,6 +26,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsmdl.so"
 SMDL_PER_SUBSET_LAUNCH = 1
 SMDL_NO_GRAPH = 2
 SMDL_COMPOSE_CODES = 4
+SMDL_DETERMINISTIC = 8
+SMDL_CHECK_FINITE = 16
 
 _STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_UNSUPPORTED", -4: "E_NOMEM", -5: "E_HIP",
            -6: "E_NUMERIC", -7: "E_STATE"}
@@ -49,7 +51,7 @@ class _Subsets(C.Structure):
 class _LearnOpts(C.Structure):
     _fields_ = [("iters_local", C.c_int), ("iters_merge", C.c_int), ("s_merge", C.c_int),
                 ("s_final", C.c_int), ("flags", C.c_uint32), ("D_local_init", C.c_void_p),
-                ("D_merge_init", C.c_void_p)]
+                ("D_merge_init", C.c_void_p), ("merge_seed", C.c_uint64), ("X_local", _Codes)]
 
 
 class _TrainOpts(C.Structure):
@@ -91,6 +93,7 @@ def _load():
         "smdl_set_tile": [vp, i32, i32, i32, i32],
         "smdl_set_mod_solver": [vp, i32],
         "smdl_set_autotune": [vp, i32],
+        "smdl_set_flags": [vp, C.c_uint32],
         "smdl_phase_ms": [vp, C.POINTER(C.c_float)],
         "smdl_last_kernel_ms": [vp, C.POINTER(C.c_float)],
     }
@@ -243,9 +246,12 @@ class Handle:
     def split_merge_learn(self, Y: torch.Tensor, perm: torch.Tensor | None, offsets, K_local, s_local,
                           K: int, iters_local: int, iters_merge: int, s_merge: int, s_final: int,
                           flags: int = 0, codes: bool = True, local: bool = False,
-                          D_local_init: torch.Tensor | None = None, D_merge_init: torch.Tensor | None = None):
+                          D_local_init: torch.Tensor | None = None, D_merge_init: torch.Tensor | None = None,
+                          merge_seed: int = 0, X_local: "Codes | None" = None):
         """Algorithm 1.  Returns (D, codes or None, D_local or None, scales (np.float64[L])).
-        D_local_init (max K_local, m) and D_merge_init (K, m) replace the first-columns starts."""
+        D_local_init (max K_local, m) and D_merge_init (K, m) replace the first-columns starts;
+        merge_seed != 0 starts the merge from a seeded permutation of the pooled columns;
+        X_local (N rows, s >= max s_local) receives the final local codes in split order."""
         _dev_tensor(Y, torch.float32, "Y")
         N, m = Y.shape
         offsets = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -262,9 +268,15 @@ class Handle:
             _dev_tensor(D_local_init, torch.float32, "D_local_init", (int(K_local.max()), m))
         if D_merge_init is not None:
             _dev_tensor(D_merge_init, torch.float32, "D_merge_init", (K, m))
+        if X_local is not None:
+            for t_, nm in ((X_local.idx, "X_local.idx"), (X_local.coef, "X_local.coef"), (X_local.nnz, "X_local.nnz")):
+                _dev_tensor(t_, t_.dtype, nm)
+            if X_local.idx.shape[0] != N:
+                raise ValueError("X_local must have N rows")
         opts = _LearnOpts(iters_local, iters_merge, s_merge, s_final, flags,
                           _ptr(D_local_init).value if D_local_init is not None else None,
-                          _ptr(D_merge_init).value if D_merge_init is not None else None)
+                          _ptr(D_merge_init).value if D_merge_init is not None else None,
+                          int(merge_seed), X_local._c() if X_local is not None else _Codes(None, None, None, 0))
         D = torch.empty((K, m), dtype=torch.float32, device=Y.device)
         s_out = int(s_local.max()) * s_merge if flags & SMDL_COMPOSE_CODES else s_final
         X = Codes.empty(N, s_out, Y.device) if codes else None
@@ -326,6 +338,10 @@ class Handle:
     def set_mod_solver(self, mode: int):
         """0 automatic, 1 multi-work-group panels, 2 one work group per dictionary."""
         self._check(lib().smdl_set_mod_solver(self._h, mode))
+
+    def set_flags(self, flags: int):
+        """Handle-wide options: SMDL_DETERMINISTIC | SMDL_CHECK_FINITE (0 clears)."""
+        self._check(lib().smdl_set_flags(self._h, int(flags)))
 
     def set_autotune(self, enabled: bool):
         self._check(lib().smdl_set_autotune(self._h, 1 if enabled else 0))

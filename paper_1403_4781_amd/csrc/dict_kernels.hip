@@ -84,17 +84,18 @@ __global__ __launch_bounds__(256) void gram_kernel(const GramDesc* __restrict__ 
         }
 }
 
-// out[:, n] = Y[:, perm[n]]  (m floats per column); an index outside [0, N) writes zeros and
-// raises *bad.
+// out[:, n] = Y[:, perm[n]]  (m floats per column); an index outside [0, n_src) writes zeros
+// and raises *bad.
 __global__ void gather_columns_kernel(const float* __restrict__ Y, const int64_t* __restrict__ perm,
-                                      int64_t N, int m, float* __restrict__ out, int32_t* __restrict__ bad) {
+                                      int64_t N, int64_t n_src, int m, float* __restrict__ out,
+                                      int32_t* __restrict__ bad) {
     const int64_t total = N * m;
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
          f += (int64_t)gridDim.x * blockDim.x) {
         const int64_t n = f / m;
         const int r = (int)(f - n * m);
         const int64_t src = perm[n];
-        if (src < 0 || src >= N) {
+        if (src < 0 || src >= n_src) {
             out[f] = 0.f;
             if (r == 0) atomicOr(bad, 1);
         } else {
@@ -275,10 +276,24 @@ hipError_t launch_gram_batched(const void* dev_gram_desc, int n_dict, int max_kp
     return hipGetLastError();
 }
 
-hipError_t launch_gather_columns(const float* Y, const int64_t* perm, int64_t N, int m, float* out,
-                                 int32_t* bad, hipStream_t st) {
+// *bad = 1 when any of the n values is not finite (NaN or infinite).
+__global__ void check_finite_kernel(const float* __restrict__ x, int64_t n, int32_t* __restrict__ bad) {
+    bool ok = true;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        ok &= isfinite(x[i]);
+    if (__any(!ok) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+hipError_t launch_check_finite(const float* x, int64_t n, int32_t* bad, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_columns(const float* Y, const int64_t* perm, int64_t N, int64_t n_src, int m,
+                                 float* out, int32_t* bad, hipStream_t st) {
     hipLaunchKernelGGL(gather_columns_kernel, dim3(grid_for(N * m, 256)), dim3(256), 0, st, Y, perm,
-                       N, m, out, bad);
+                       N, n_src, m, out, bad);
     return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ __device__ __forceinline__ int clamp_nnz(int k, int s) { return k < 0 ? 0 : (k >
 constexpr int CSC_SIG = 1024;
 
 __global__ __launch_bounds__(256) void csc_count_kernel(const ModDesc* __restrict__ md, int32_t* __restrict__ cnt,
-                                                        int32_t* __restrict__ status) {
+                                                        int32_t* __restrict__ status, int32_t* __restrict__ bcnt,
+                                                        int total_atoms) {
     const ModDesc d = md[blockIdx.y];
     __shared__ int32_t hist[SMDL_MAX_K];
     const int tid = threadIdx.x;
@@ -61,8 +62,73 @@ __global__ __launch_bounds__(256) void csc_count_kernel(const ModDesc* __restric
     }
     if (bad) atomicOr(&status[8 * blockIdx.y + 3], 1);
     __syncthreads();
-    for (int a = tid; a < d.K; a += 256)
+    for (int a = tid; a < d.K; a += 256) {
         if (hist[a]) atomicAdd(&cnt[d.atom0 + a], hist[a]);
+        // fixed-order mode: this block's count of every atom (zeros included)
+        if (bcnt) bcnt[(int64_t)blockIdx.x * total_atoms + d.atom0 + a] = hist[a];
+    }
+}
+
+// Fixed-order mode: the first list position of block b's entries of every atom, the blocks in
+// order after the atom's list start (one thread per atom).
+__global__ void csc_block_base_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ bcnt,
+                                      int32_t* __restrict__ bbase, int total_atoms, int nblk) {
+    const int ga = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ga >= total_atoms) return;
+    int32_t run = ptr[ga];
+    for (int b = 0; b < nblk; ++b) {
+        bbase[(int64_t)b * total_atoms + ga] = run;
+        run += bcnt[(int64_t)b * total_atoms + ga];
+    }
+}
+
+// Fixed-order mode: one wave per block of CSC_SIG signals places the block's entries from its
+// bases in a fixed order (chunks of 64 signals, within a chunk slot by slot, within a slot by
+// signal): the lanes holding the same atom take consecutive positions by lane order (ballot and
+// rank), one atom per round.  The lists, and so the order of every product sum, are then the
+// same on every run.
+__global__ __launch_bounds__(64) void csc_fill_fixed_kernel(const ModDesc* __restrict__ md,
+                                                            const int32_t* __restrict__ bbase, int total_atoms,
+                                                            int32_t* __restrict__ list_sig,
+                                                            float* __restrict__ list_coef) {
+    const ModDesc d = md[blockIdx.y];
+    __shared__ int32_t cur[SMDL_MAX_K];
+    const int lane = threadIdx.x;
+    for (int a = lane; a < d.K; a += 64) cur[a] = bbase[(int64_t)blockIdx.x * total_atoms + d.atom0 + a];
+    __syncthreads();
+    const int64_t n0 = (int64_t)blockIdx.x * CSC_SIG, n1 = min(d.n, n0 + CSC_SIG);
+    const uint64_t lower = (1ull << lane) - 1ull;
+    for (int64_t nb = n0; nb < n1; nb += 64) {
+        const int64_t n = nb + lane;
+        const bool valid = n < n1;
+        const int k = valid ? clamp_nnz(d.nnz[n], d.s_stride) : 0;
+        for (int i = 0; i < d.s_stride; ++i) {
+            int ix = -1;
+            float cf = 0.f;
+            if (i < k) {
+                ix = d.idx[n * d.s_stride + i];
+                cf = d.coef[n * d.s_stride + i];
+            }
+            bool todo = ix >= 0 && ix < d.K;
+            for (;;) {
+                const uint64_t act = __ballot(todo);
+                if (!act) break;
+                const int first = __builtin_ctzll(act);
+                const int u = __shfl(ix, first, 64);
+                const bool mine = todo && ix == u;
+                const uint64_t grp = __ballot(mine);
+                const int base = cur[u];
+                if (mine) {
+                    const int pos = base + __popcll(grp & lower);
+                    list_sig[pos] = (int32_t)n;
+                    list_coef[pos] = cf;
+                    todo = false;
+                }
+                if (lane == 0) cur[u] = base + __popcll(grp);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
 }
 
 // Exclusive scan of cnt[0..total) into ptr[0..total]; single block of 1024 threads.
@@ -136,7 +202,7 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
                                                            const int32_t* __restrict__ list_sig,
                                                            const float* __restrict__ list_coef,
                                                            const double* __restrict__ arena, double* __restrict__ part,
-                                                           int64_t arena_len) {
+                                                           int64_t arena_len, int fixed_order) {
     const ModDesc d = md[blockIdx.y];
     const int a = blockIdx.x;
     const int c = blockIdx.z, P = gridDim.z;
@@ -170,16 +236,25 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
                 s_cf[q] = list_coef[p0 + q];
             }
             __syncthreads();
-            // A column: every entry (n, x_na) adds x_na * x_nl at every atom l of signal n
-            for (int q = tid; q < cnt; q += 256) {
+            // A column: every entry (n, x_na) adds x_na * x_nl at every atom l of signal n; in the
+            // fixed-order mode one thread adds them in list order
+            auto add_entry = [&](int q, bool atomic) {
                 const int64_t n = s_sig[q];
                 const double xa = s_cf[q];
                 const int k = clamp_nnz(d.nnz[n], d.s_stride);
                 for (int i = 0; i < k; ++i) {
                     const int l = d.idx[n * d.s_stride + i];
                     if (l < 0 || l >= d.K) continue;
-                    atomicAdd(&colA[l], xa * (double)d.coef[n * d.s_stride + i]);
+                    const double v = xa * (double)d.coef[n * d.s_stride + i];
+                    if (atomic) atomicAdd(&colA[l], v);
+                    else colA[l] += v;
                 }
+            };
+            if (fixed_order) {
+                if (tid == 0)
+                    for (int q = 0; q < cnt; ++q) add_entry(q, false);
+            } else {
+                for (int q = tid; q < cnt; q += 256) add_entry(q, true);
             }
             // B column: rows split over threads, entries over groups of threads, PB signal
             // loads in flight per thread (the sum keeps the order of the entries)
@@ -1082,24 +1157,37 @@ static bool mod_solve_multi(int n_desc, int solver) {
     return n_desc < 256;
 }
 
+int64_t mod_csc_blocks(int64_t max_n) { return std::max<int64_t>(1, (max_n + CSC_SIG - 1) / CSC_SIG); }
+
 hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atoms, int64_t max_n, int32_t* cnt,
                       int32_t* fill, int32_t* ptr, int32_t* list_sig, float* list_coef, int32_t* status,
                       int max_kpad, double* arena, double* part, int64_t arena_len, int chunks, int solver,
-                      hipStream_t st) {
+                      int32_t* bcnt, int32_t* bbase, hipStream_t st) {
     hipError_t e;
     if (chunks < 1 || (chunks > 1 && !part)) return hipErrorInvalidValue;
+    const bool fixed = bcnt != nullptr;
+    if (fixed && !bbase) return hipErrorInvalidValue;
     if ((e = launch_zero_i32(cnt, total_atoms, st)) != hipSuccess) return e;
     if ((e = launch_zero_i32(fill, total_atoms, st)) != hipSuccess) return e;
     const unsigned csc_blocks = (unsigned)std::max<int64_t>(1, (max_n + CSC_SIG - 1) / CSC_SIG);
-    hipLaunchKernelGGL(csc_count_kernel, dim3(csc_blocks, n_desc), dim3(256), 0, st, dev_desc, cnt, status);
+    hipLaunchKernelGGL(csc_count_kernel, dim3(csc_blocks, n_desc), dim3(256), 0, st, dev_desc, cnt, status, bcnt,
+                       total_atoms);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, cnt, total_atoms, ptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(csc_fill_kernel, dim3(csc_blocks, n_desc), dim3(256), 0, st, dev_desc, ptr,
-                       fill, list_sig, list_coef);
+    if (fixed) {
+        hipLaunchKernelGGL(csc_block_base_kernel, dim3((total_atoms + 255) / 256), dim3(256), 0, st, ptr, bcnt, bbase,
+                           total_atoms, (int)csc_blocks);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(csc_fill_fixed_kernel, dim3(csc_blocks, n_desc), dim3(64), 0, st, dev_desc, bbase,
+                           total_atoms, list_sig, list_coef);
+    } else {
+        hipLaunchKernelGGL(csc_fill_kernel, dim3(csc_blocks, n_desc), dim3(256), 0, st, dev_desc, ptr,
+                           fill, list_sig, list_coef);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(mod_products_kernel, dim3(max_kpad, n_desc, chunks), dim3(256), 0, st, dev_desc, m, ptr,
-                       list_sig, list_coef, arena, part, arena_len);
+                       list_sig, list_coef, arena, part, arena_len, fixed ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (chunks > 1) {
         const unsigned g = (unsigned)std::min<int64_t>(4096, (arena_len + 255) / 256);

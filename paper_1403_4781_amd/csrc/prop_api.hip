@@ -429,13 +429,7 @@ extern "C" smdl_status smdl_prop_train(smdl_t h, smdl_prop_t p, const float* Y, 
     if (e != hipSuccess) return h->hip(e, "labels");
     std::vector<int32_t> order(N);
     std::iota(order.begin(), order.end(), 0);
-    uint64_t rng = o->shuffle_seed;
-    auto next = [&rng]() {   // splitmix64
-        uint64_t z = (rng += 0x9E3779B97F4A7C15ull);
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        return z ^ (z >> 31);
-    };
+    SplitMix64 rng(o->shuffle_seed);
     // One epoch (every Adam step over the batches of `rows`) is captured once as a graph and
     // replayed per epoch; the shuffled order is copied into `rows` before each replay and the
     // Adam step count lives on the device.
@@ -475,16 +469,17 @@ extern "C" smdl_status smdl_prop_train(smdl_t h, smdl_prop_t p, const float* Y, 
     const bool keep_all = (int64_t)o->epochs * N <= (int64_t)1 << 26;
     std::vector<std::vector<int32_t>> orders;
     for (int ep = 0; ep < o->epochs; ++ep) {
+        // with one shared buffer, the previous epoch's queued copy must have read it before the
+        // shuffle below rewrites it
+        if (!keep_all && ep > 0 && nb > 0 && (st = h->hip(hipStreamSynchronize(h->stream), "train")) != SMDL_OK) {
+            cleanup();
+            return st;
+        }
         if (o->shuffle_seed) {
-            for (int64_t i = N - 1; i > 0; --i) std::swap(order[i], order[next() % (uint64_t)(i + 1)]);
+            for (int64_t i = N - 1; i > 0; --i) std::swap(order[i], order[rng.next() % (uint64_t)(i + 1)]);
         }
         if (nb > 0) {
-            if (keep_all) {
-                orders.push_back(order);
-            } else if (ep > 0 && (st = h->hip(hipStreamSynchronize(h->stream), "train")) != SMDL_OK) {
-                cleanup();
-                return st;
-            }
+            if (keep_all) orders.push_back(order);
             const int32_t* src = keep_all ? orders.back().data() : order.data();
             if ((st = h->hip(hipMemcpyAsync(rows, src, (size_t)N * 4, hipMemcpyHostToDevice, h->stream), "rows")) != SMDL_OK ||
                 (st = h->hip(hipGraphLaunch(exec, h->stream), "graph launch")) != SMDL_OK) {

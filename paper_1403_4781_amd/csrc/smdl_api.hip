@@ -117,6 +117,20 @@ smdl_status check_dims(smdl_t h, int m, int K, int s) {
     return SMDL_OK;
 }
 
+smdl_status check_finite(smdl_t h, const float* x, int64_t n, const char* what) {
+    if (n <= 0) return SMDL_OK;
+    int32_t* bad = (int32_t*)h->ws("finite.bad", 64);
+    if (!bad) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    smdl_status st;
+    if ((st = h->hip(launch_zero_i32(bad, 1, h->stream), "zero")) != SMDL_OK) return st;
+    if ((st = h->hip(launch_check_finite(x, n, bad, h->stream), "finite check")) != SMDL_OK) return st;
+    int32_t hb = 0;
+    if ((st = h->hip(hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, h->stream), "finite check")) != SMDL_OK) return st;
+    if ((st = h->hip(hipStreamSynchronize(h->stream), "finite check")) != SMDL_OK) return st;
+    if (hb) return h->fail(SMDL_E_NUMERIC, std::string(what) + " holds a non-finite value");
+    return SMDL_OK;
+}
+
 smdl_status check_codes(smdl_t h, const smdl_codes& X, int64_t N, int s_needed) {
     if (N > 0 && (!X.idx || !X.coef || !X.nnz)) return h->fail(SMDL_E_ARG, "null code array");
     if (X.s_max < s_needed) return h->fail(SMDL_E_ARG, "codes.s_max smaller than the sparsity");
@@ -393,6 +407,9 @@ extern "C" smdl_status smdl_omp_code(smdl_t h, const float* D, int m, int K, con
     if (!D || !Y) return h->fail(SMDL_E_ARG, "null pointer");
     if (N > (int64_t)INT32_MAX * 16) return h->fail(SMDL_E_SHAPE, "N too large");
     (void)hipSetDevice(h->device);
+    if ((h->flags & SMDL_CHECK_FINITE) &&
+        ((st = check_finite(h, D, (int64_t)K * m, "D")) != SMDL_OK || (st = check_finite(h, Y, N * m, "Y")) != SMDL_OK))
+        return st;
     if ((st = omp_code_impl(h, D, m, K, Y, N, s_max, eps, X, res_norm, nullptr, nullptr, 0, "omp")) != SMDL_OK)
         return st;
     st = h->hip(hipStreamSynchronize(h->stream), "omp");
@@ -405,7 +422,7 @@ extern "C" smdl_status smdl_omp_code(smdl_t h, const float* D, int m, int K, con
 // ------------------------------------------------------------------------------------------
 
 smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, const char* tag,
-                        ModPlan& plan) {
+                        ModPlan& plan, bool fixed_order) {
     std::string t(tag);
     int64_t total_atoms = 0, entries = 0, max_n = 0;
     size_t abytes = 0;
@@ -442,6 +459,12 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
     plan.arena = A;
     plan.arena_len = (int64_t)(abytes / 8);
     plan.part = plan.chunks > 1 ? (double*)h->ws((t + ".part").c_str(), abytes * (plan.chunks - 1)) : nullptr;
+    if (fixed_order) {
+        const size_t nb = (size_t)mod_csc_blocks(max_n) * (size_t)std::max<int64_t>(1, total_atoms) * 4;
+        plan.bcnt = (int32_t*)h->ws((t + ".bcnt").c_str(), nb);
+        plan.bbase = (int32_t*)h->ws((t + ".bbase").c_str(), nb);
+        if (!plan.bcnt || !plan.bbase) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    }
     if (!A || !W || !Ld || !plan.cnt || !plan.fill || !plan.ptr || !plan.list_sig || !plan.list_coef ||
         !plan.status || !plan.desc || (plan.chunks > 1 && !plan.part))
         return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
@@ -466,7 +489,7 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
 hipError_t enqueue_mod(smdl_t h, const ModPlan& plan) {
     return launch_mod(plan.desc, plan.n_desc, plan.m, plan.total_atoms, plan.max_n, plan.cnt, plan.fill, plan.ptr,
                       plan.list_sig, plan.list_coef, plan.status, plan.maxKpad, plan.arena, plan.part,
-                      plan.arena_len, plan.chunks, plan.solver, h->stream);
+                      plan.arena_len, plan.chunks, plan.solver, plan.bcnt, plan.bbase, h->stream);
 }
 
 // Read the MOD status array; returns SMDL_E_NUMERIC / SMDL_E_ARG on failures.
@@ -495,10 +518,11 @@ extern "C" smdl_status smdl_mod_update(smdl_t h, const float* Y, int m, int64_t 
     if (!D || (N > 0 && (!Y || !X.idx || !X.coef || !X.nnz))) return h->fail(SMDL_E_ARG, "null pointer");
     if (N * X.s_max > INT32_MAX) return h->fail(SMDL_E_SHAPE, "too many code entries");
     (void)hipSetDevice(h->device);
+    if ((h->flags & SMDL_CHECK_FINITE) && (st = check_finite(h, Y, N * m, "Y")) != SMDL_OK) return st;
     std::vector<ModSpec> specs(1);
     specs[0] = ModSpec{Y, X.idx, X.coef, X.nnz, N, D, K, X.s_max};
     ModPlan plan;
-    if ((st = prepare_mod(h, m, specs, "mod", plan)) != SMDL_OK) return st;
+    if ((st = prepare_mod(h, m, specs, "mod", plan, (h->flags & SMDL_DETERMINISTIC) != 0)) != SMDL_OK) return st;
     if ((st = h->hip(enqueue_mod(h, plan), "mod launch")) != SMDL_OK) return st;
     std::vector<int32_t> s4;
     st = read_mod_status(h, plan, &s4);
@@ -591,7 +615,8 @@ smdl_status learn_sets(smdl_t h, int m, std::vector<SetSpec>& sets, int iters, c
             x.s_stride = out.s_stride;
             ms.push_back(x);
         }
-        if ((st = prepare_mod(h, m, ms, (gt + "m").c_str(), mplans[gi])) != SMDL_OK) return st;
+        if ((st = prepare_mod(h, m, ms, (gt + "m").c_str(), mplans[gi], (flags & SMDL_DETERMINISTIC) != 0)) != SMDL_OK)
+            return st;
         if (h->autotune && !per_set &&
             (st = autotune_plan(h, cplans[gi], groups[gi], out, cplans[gi].persistent, gt.c_str())) != SMDL_OK)
             return st;
@@ -660,6 +685,7 @@ static smdl_status learn_impl(smdl_t h, const float* Y, int m, int64_t N, int K,
     if (X_out.idx && (st = check_codes(h, X_out, N, s)) != SMDL_OK) return st;
     if (N * 16 > INT32_MAX) return h->fail(SMDL_E_SHAPE, "N too large for one data set");
     (void)hipSetDevice(h->device);
+    if ((h->flags & SMDL_CHECK_FINITE) && (st = check_finite(h, Y, N * m, "Y")) != SMDL_OK) return st;
     CodeOut out;
     if (X_out.idx) {
         out = CodeOut{X_out.idx, X_out.coef, X_out.nnz, nullptr, X_out.s_max};
@@ -679,7 +705,7 @@ static smdl_status learn_impl(smdl_t h, const float* Y, int m, int64_t N, int K,
     sets[0].s = s;
     sets[0].D = D_out;
     sets[0].out0 = 0;
-    return learn_sets(h, m, sets, iters, out, X_out.idx != nullptr, 0, "learn");
+    return learn_sets(h, m, sets, iters, out, X_out.idx != nullptr, h->flags & SMDL_DETERMINISTIC, "learn");
 }
 
 extern "C" smdl_status smdl_learn(smdl_t h, const float* Y, int m, int64_t N, int K, int s, int iters,
@@ -720,8 +746,14 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
     }
     if (sumK < K) return h->fail(SMDL_E_ARG, "the pooled local atoms must number at least K");
     if (sumK * 16 > INT32_MAX) return h->fail(SMDL_E_SHAPE, "too many pooled atoms");
-    const bool compose = (o->flags & SMDL_COMPOSE_CODES) != 0;
+    const uint32_t flags = o->flags | h->flags;
+    const bool compose = (flags & SMDL_COMPOSE_CODES) != 0;
     if (X_out.idx && !compose && (st = check_codes(h, X_out, N, o->s_final)) != SMDL_OK) return st;
+    if (o->X_local.idx) {
+        if (!o->X_local.coef || !o->X_local.nnz) return h->fail(SMDL_E_ARG, "null local code array");
+        if (o->X_local.s_max < s_loc_max || o->X_local.s_max > SMDL_MAX_S)
+            return h->fail(SMDL_E_ARG, "X_local.s_max must be in [max s_local, 16]");
+    }
     if (X_out.idx && compose) {
         if (!X_out.coef || !X_out.nnz) return h->fail(SMDL_E_ARG, "null code array");
         if (s_loc_max * o->s_merge > SMDL_MAX_COMPOSED)
@@ -730,6 +762,7 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
             return h->fail(SMDL_E_ARG, "composed codes need s_local * s_merge <= codes.s_max <= 64");
     }
     (void)hipSetDevice(h->device);
+    if ((flags & SMDL_CHECK_FINITE) && (st = check_finite(h, Y, N * m, "Y")) != SMDL_OK) return st;
 
     // step 1: the subsets as contiguous blocks of a permuted copy of Y
     const float* Yp = Y;
@@ -739,7 +772,7 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
         int32_t* bad = (int32_t*)h->ws("sm.bad", 64);
         if (!bad) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
         if ((st = h->hip(launch_zero_i32(bad, 1, h->stream), "zero")) != SMDL_OK) return st;
-        if ((st = h->hip(launch_gather_columns(Y, sub->perm, N, m, buf, bad, h->stream), "gather")) != SMDL_OK) return st;
+        if ((st = h->hip(launch_gather_columns(Y, sub->perm, N, N, m, buf, bad, h->stream), "gather")) != SMDL_OK) return st;
         int32_t hbad = 0;
         if ((st = h->hip(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, h->stream), "check")) != SMDL_OK) return st;
         if ((st = h->hip(hipStreamSynchronize(h->stream), "gather")) != SMDL_OK) return st;
@@ -778,8 +811,22 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
         sets[t].out0 = sub->offsets[t];
     }
     auto t0 = std::chrono::steady_clock::now();
-    if ((st = learn_sets(h, m, sets, o->iters_local, lc, true, o->flags, "sm.loc")) != SMDL_OK) return st;
+    if ((st = learn_sets(h, m, sets, o->iters_local, lc, true, flags, "sm.loc")) != SMDL_OK) return st;
     auto t1 = std::chrono::steady_clock::now();
+    if (o->X_local.idx) {
+        // the final local codes X^(t), rows in split order
+        const smdl_codes& xl = o->X_local;
+        if ((st = h->hip(launch_fill_codes(xl.idx, xl.coef, xl.nnz, N, xl.s_max, h->stream), "local codes")) != SMDL_OK ||
+            (st = h->hip(hipMemcpy2DAsync(xl.idx, (size_t)xl.s_max * 4, lc.idx, (size_t)lc.s_stride * 4,
+                                          (size_t)lc.s_stride * 4, N, hipMemcpyDeviceToDevice, h->stream),
+                         "local codes")) != SMDL_OK ||
+            (st = h->hip(hipMemcpy2DAsync(xl.coef, (size_t)xl.s_max * 4, lc.coef, (size_t)lc.s_stride * 4,
+                                          (size_t)lc.s_stride * 4, N, hipMemcpyDeviceToDevice, h->stream),
+                         "local codes")) != SMDL_OK ||
+            (st = h->hip(hipMemcpyAsync(xl.nnz, lc.nnz, (size_t)N * 4, hipMemcpyDeviceToDevice, h->stream),
+                         "local codes")) != SMDL_OK)
+            return st;
+    }
 
     // step 3: scales, pooled data, merge
     if ((st = h->hip(launch_code_scales(lc.coef, lc.nnz, lc.s_stride, offs_dev, L, scales, h->stream), "scales")) != SMDL_OK)
@@ -793,15 +840,34 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
     mc.nnz = (int32_t*)h->ws("sm.mnnz", (size_t)sumK * 4);
     mc.res = nullptr;
     if (!mc.idx || !mc.coef || !mc.nnz) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    const float* merge_init = o->D_merge_init;
+    if (!merge_init && o->merge_seed) {
+        // the first K columns of a seeded permutation of the pooled columns
+        std::vector<int64_t> pc((size_t)sumK);
+        for (int64_t i = 0; i < sumK; ++i) pc[(size_t)i] = i;
+        seeded_shuffle(pc, o->merge_seed);
+        int64_t* cols = (int64_t*)h->ws("sm.mcols", (size_t)K * 8);
+        float* minit = (float*)h->ws("sm.minit", (size_t)K * m * 4);
+        int32_t* bad = (int32_t*)h->ws("sm.mbad", 64);
+        if (!cols || !minit || !bad) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+        if ((st = h->hip(hipMemcpyAsync(cols, pc.data(), (size_t)K * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK ||
+            (st = h->hip(launch_zero_i32(bad, 1, h->stream), "zero")) != SMDL_OK ||
+            (st = h->hip(launch_gather_columns(Ytil, cols, K, sumK, m, minit, bad, h->stream), "merge start")) != SMDL_OK)
+            return st;
+        // the host vector must outlive the queued copy
+        if ((st = h->hip(hipStreamSynchronize(h->stream), "merge start")) != SMDL_OK) return st;
+        merge_init = minit;
+    }
     std::vector<SetSpec> ms(1);
     ms[0].Y = Ytil;
-    ms[0].init = o->D_merge_init;
+    ms[0].init = merge_init;
     ms[0].n = sumK;
     ms[0].K = K;
     ms[0].s = o->s_merge;
     ms[0].D = D_out;
     ms[0].out0 = 0;
-    if ((st = learn_sets(h, m, ms, o->iters_merge, mc, compose && X_out.idx, o->flags & SMDL_NO_GRAPH, "sm.mrg")) !=
+    if ((st = learn_sets(h, m, ms, o->iters_merge, mc, compose && X_out.idx, flags & (SMDL_NO_GRAPH | SMDL_DETERMINISTIC),
+                         "sm.mrg")) !=
         SMDL_OK)
         return st;
     auto t2 = std::chrono::steady_clock::now();
@@ -939,6 +1005,14 @@ extern "C" smdl_status smdl_set_mod_solver(smdl_t h, int mode) {
     if (!h) return SMDL_E_ARG;
     if (mode < 0 || mode > 2) return h->fail(SMDL_E_ARG, "MOD solver mode must be 0, 1 or 2");
     h->mod_solver = mode;
+    return SMDL_OK;
+}
+
+extern "C" smdl_status smdl_set_flags(smdl_t h, uint32_t flags) {
+    if (!h) return SMDL_E_ARG;
+    if (flags & ~(SMDL_DETERMINISTIC | SMDL_CHECK_FINITE))
+        return h->fail(SMDL_E_ARG, "only SMDL_DETERMINISTIC and SMDL_CHECK_FINITE apply to a handle");
+    h->flags = flags;
     return SMDL_OK;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <utility>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -13,6 +14,26 @@
 // distance to the span of the chosen ones is at most SMDL_DEP_TOL * ||d_j||^2.
 constexpr float SMDL_TAU = 1e-5f;
 constexpr float SMDL_DEP_TOL = 1e-5f;
+
+// splitmix64 (Steele, Lea, Flood 2014): the host-side generator of the seeded orders the
+// library draws itself (training shuffles, the seeded merge start).
+struct SplitMix64 {
+    uint64_t state;
+    explicit SplitMix64(uint64_t seed) : state(seed) {}
+    uint64_t next() {
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+
+// Fisher-Yates from the last position down: position i swaps with position next() % (i + 1).
+template <typename T>
+void seeded_shuffle(std::vector<T>& v, uint64_t seed) {
+    SplitMix64 g(seed);
+    for (int64_t i = (int64_t)v.size() - 1; i > 0; --i) std::swap(v[i], v[g.next() % (uint64_t)(i + 1)]);
+}
 
 struct Buf {
     void* p = nullptr;
@@ -29,6 +50,7 @@ struct smdl_ctx {
     std::map<std::tuple<int, int, int>, OmpTile> tiles;
     bool autotune = true;
     int mod_solver = 0;                         // 0 automatic, 1 multi-work-group, 2 one work group
+    uint32_t flags = 0;                         // SMDL_DETERMINISTIC | SMDL_CHECK_FINITE for every call
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed_pending = false;
     float last_kernel_ms = 0.f;
@@ -97,10 +119,13 @@ struct ModPlan {
     int64_t arena_len = 0;                      // doubles
     int chunks = 1;                             // blocks per atom in the products
     int solver = 0;                             // the handle's mod_solver
+    int32_t *bcnt = nullptr, *bbase = nullptr;  // per-block counts and bases (fixed-order mode)
     std::vector<ModDesc> host_desc;
 };
 
 smdl_status check_dims(smdl_t h, int m, int K, int s);
+// SMDL_E_NUMERIC if any of the n floats at x (device) is not finite (synchronises the stream).
+smdl_status check_finite(smdl_t h, const float* x, int64_t n, const char* what);
 smdl_status check_codes(smdl_t h, const smdl_codes& X, int64_t N, int s_needed);
 OmpTile default_tile(int Kpad, int s, int lanes_ok = 16 | 32 | 64);
 OmpTile choose_tile(smdl_t h, int Kpad, int s, bool batched, int lanes_ok = 16 | 32 | 64);

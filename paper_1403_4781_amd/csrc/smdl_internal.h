@@ -118,15 +118,21 @@ struct ModDesc {
 // descriptor (arena_len doubles, the descriptors' A pointers inside it); with chunks > 1 every
 // atom's products are split over that many blocks and part holds (chunks - 1) x arena_len
 // doubles of partial sums.  solver: 0 picks the factorisation by the number of dictionaries,
-// 1 forces the multi-work-group panels, 2 one work group per dictionary.
+// 1 forces the multi-work-group panels, 2 one work group per dictionary.  bcnt, bbase: NULL, or
+// (fixed-order mode) two int32 arrays of mod_csc_blocks(max_n) x total_atoms entries each.
 hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atoms, int64_t max_n, int32_t* cnt,
                       int32_t* fill, int32_t* ptr, int32_t* list_sig, float* list_coef, int32_t* status,
                       int max_kpad, double* arena, double* part, int64_t arena_len, int chunks, int solver,
-                      hipStream_t st);
+                      int32_t* bcnt, int32_t* bbase, hipStream_t st);
+// Blocks of the code transpose for sets of at most max_n signals.
+int64_t mod_csc_blocks(int64_t max_n);
 
 // Misc kernels.
-hipError_t launch_gather_columns(const float* Y, const int64_t* perm, int64_t N, int m, float* out,
-                                 int32_t* bad, hipStream_t st);
+// *bad (zeroed by the caller) becomes 1 when any of the n floats at x is not finite.
+hipError_t launch_check_finite(const float* x, int64_t n, int32_t* bad, hipStream_t st);
+// out[:, n] = Y[:, perm[n]] for n < N; an entry outside [0, n_src) writes zeros and sets *bad.
+hipError_t launch_gather_columns(const float* Y, const int64_t* perm, int64_t N, int64_t n_src, int m,
+                                 float* out, int32_t* bad, hipStream_t st);
 hipError_t launch_init_from_columns_batched(const void* dev_init_desc, int n_dict, int max_k,
                                             int m, hipStream_t st);
 struct InitDesc {

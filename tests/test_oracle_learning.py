@@ -107,3 +107,30 @@ def test_proposition_1_on_composed_codes():
             err = np.linalg.norm(sub[n] - D.T @ r)
             assert err <= Dt.shape[0] * eps2 + eps1 + 1e-12
             assert np.linalg.norm(E @ x1) <= np.sqrt(len(used)) * enorm[used].max() * np.linalg.norm(x1) + 1e-12
+
+
+def test_splitmix64_published_vectors():
+    """The generator of the seeded merge start against the published splitmix64 outputs for
+    seed 1234567 (the reference test vector of the generator)."""
+    g = oracle.splitmix64(1234567)
+    assert [next(g) for _ in range(5)] == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                                           4593380528125082431, 16408922859458223821]
+    p = oracle.seeded_permutation(1000, 99)
+    assert sorted(p.tolist()) == list(range(1000))
+    assert not np.array_equal(p, np.arange(1000))
+
+
+def test_seeded_merge_start():
+    """With a seeded merge order and no merge iterations, the merged dictionary is the first K
+    pooled columns in that order, unit-normalised: the local atoms at those positions (the
+    subset scales cancel in the normalisation)."""
+    w = synth.patch_scale(N=1200, L=3, iters=0)
+    K_local = np.array([64, 64, 64], np.int32)
+    s_local = np.array([4, 4, 4], np.int32)
+    D, _, Dl, sc = oracle.split_merge(w.Y, w.perm, w.offsets, K_local, s_local, 48, 0, 0, 4, 4, codes=False,
+                                      merge_seed=77)
+    cols = oracle.seeded_permutation(192, 77)[:48]
+    ref = Dl[cols] / np.linalg.norm(Dl[cols], axis=1, keepdims=True)
+    np.testing.assert_allclose(D, ref, atol=1e-12)
+    D0, _, _, _ = oracle.split_merge(w.Y, w.perm, w.offsets, K_local, s_local, 48, 0, 0, 4, 4, codes=False)
+    np.testing.assert_allclose(D0, Dl[:48] / np.linalg.norm(Dl[:48], axis=1, keepdims=True), atol=1e-12)
