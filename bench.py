@@ -31,13 +31,32 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-ALGO_FLOPS_NOTE = "2mK + K s(s-1) + 3Ks + 2 sum_k k(k+1) + s(s+1) flops per signal (m=64,K=256,s=8: 53656)"
+ALGO_FLOPS_NOTE = ("2mK (correlations) + K s(s-1) (correlation updates) + sum_k [(k-1)^2 + 2k^2] "
+                   "(Cholesky rows and coefficients) flops per signal (m=64,K=256,s=8: 47652); the s K "
+                   "argmax compares are counted apart as ALU operations")
+
+FP32_PEAK = 157.3          # TFLOP/s, MI355X dense FP32 (matrix cores; vector with packed FP32)
+FP32_VALU_UNPACKED = 78.6  # TFLOP/s, MI355X FP32 vector issue without packed FP32 instructions
 
 
 def omp_flops_per_signal(m: int, K: int, s: int) -> int:
-    """Algorithmic FP32 flops of one OMP coding (correlations, greedy updates, Cholesky data,
-    final back-substitution)."""
-    return 2 * m * K + K * s * (s - 1) + 3 * K * s + 2 * sum(k * (k + 1) for k in range(s)) + s * (s + 1)
+    """Algorithmic FP32 flops of one OMP coding: the correlations D^T y, the correlation
+    updates of the greedy steps and the Cholesky data and coefficients."""
+    return 2 * m * K + K * s * (s - 1) + sum((k - 1) ** 2 + 2 * k * k for k in range(1, s + 1))
+
+
+def omp_alu_ops_per_signal(K: int, s: int) -> int:
+    """The argmax compares of the greedy steps (s passes over K correlations)."""
+    return s * K
+
+
+def omp_mix_ceiling(m: int, K: int, s: int) -> float:
+    """The ceiling this build's flop mix faces: the correlations on the FP32 matrix cores at
+    157.3 TFLOP/s, the rest on the vector ALUs, which issue at most 78.6 TFLOP/s without packed
+    FP32 instructions (this build does not emit them): the harmonic combination."""
+    f = omp_flops_per_signal(m, K, s)
+    a0 = 2 * m * K
+    return f / (a0 / FP32_PEAK + (f - a0) / FP32_VALU_UNPACKED)
 
 
 def omp_bytes_per_signal(m: int, s: int) -> int:
@@ -85,24 +104,37 @@ def omp_kernel_name(h, m: int, K: int, s: int) -> str:
     return f"omp_fused<{kpad // lanes}, {sm}, {lanes}, {spi // 16}>"
 
 
-def cpu_baseline(w, sample_subsets: int, sample_n: int, iters: int):
-    """The FP64 oracle on a bounded sample of the same workload, timed on the host cores."""
+def cpu_baseline(w, sample_subsets: int, sample_n: int, iters: int, one_thread_subsets: int = 1):
+    """The FP64 oracle on a bounded sample of the same workload, timed on the host cores: on all
+    of them, and on one thread over a smaller sample."""
     import oracle
-    from paper_1403_4781_amd import synth
     oracle.build()
-    idx = w.perm[: sample_subsets * sample_n]
-    Ys = w.Y[idx]
-    perm = np.arange(len(idx), dtype=np.int64)
-    offs = np.arange(sample_subsets + 1, dtype=np.int64) * sample_n
-    t0 = time.perf_counter()
-    oracle.split_merge(Ys, perm, offs, [256] * sample_subsets, [8] * sample_subsets, 256, iters, iters, 4, 8)
-    dt = time.perf_counter() - t0
-    codings = sample_subsets * sample_n * (iters + 1) + len(idx)
+
+    def run(L):
+        idx = w.perm[: L * sample_n]
+        Ys = w.Y[idx]
+        perm = np.arange(len(idx), dtype=np.int64)
+        offs = np.arange(L + 1, dtype=np.int64) * sample_n
+        t0 = time.perf_counter()
+        oracle.split_merge(Ys, perm, offs, [256] * L, [8] * L, 256, iters, iters, 4, 8)
+        dt = time.perf_counter() - t0
+        return L * sample_n * (iters + 1) + len(idx), dt
+
+    codings, dt = run(sample_subsets)
     threads = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        c1, dt1 = run(one_thread_subsets)
+    finally:
+        oracle.set_threads(threads)
     return {"value": codings / dt, "unit": "signals sparse-coded/sec (m=64,K=256,s=8)", "cores": threads,
             "kind": "oracle",
             "sample": f"Algorithm 1 on {sample_subsets} subsets x {sample_n} signals of the same data, "
-                      f"{iters}+{iters} iterations, final coding of {len(idx)}: {codings} codings in {dt:.2f} s"}
+                      f"{iters}+{iters} iterations, final coding of {sample_subsets * sample_n}: {codings} codings "
+                      f"in {dt:.2f} s",
+            "value_1thread": c1 / dt1,
+            "sample_1thread": f"the same on {one_thread_subsets} subset(s) x {sample_n} signals: {c1} codings in "
+                              f"{dt1:.2f} s on one thread"}
 
 
 def run_batched(args, smdl, synth, torch, dev):
@@ -241,8 +273,11 @@ def run_large(args, smdl, synth, torch, dev):
            "learned_vs_plain": learned_sps / plain_sps, "rmse_ratio": r_learn / r_plain,
            "fallback_rate": last["nfb"] / Yev.shape[0], "learned_vs_plain_curve": curve,
            "plain_final_roofline": {"bound": "alu", "per_signal_flops": f_final,
-                                    "achieved": f_final * Yev.shape[0] / (kms * 1e-3) / 1e12, "peak": 157.3,
-                                    "unit": "TFLOP/s", "frac": f_final * Yev.shape[0] / (kms * 1e-3) / 1e12 / 157.3}}
+                                    "alu_ops_per_signal": omp_alu_ops_per_signal(1024, 16),
+                                    "achieved": f_final * Yev.shape[0] / (kms * 1e-3) / 1e12, "peak": FP32_PEAK,
+                                    "unit": "TFLOP/s",
+                                    "frac": f_final * Yev.shape[0] / (kms * 1e-3) / 1e12 / FP32_PEAK,
+                                    "mix_ceiling": omp_mix_ceiling(256, 1024, 16)}}
     print(json.dumps(out), flush=True)
 
 
@@ -636,10 +671,17 @@ def main():
         "roofline_proposer_training": train_roofline(widths, Ytr.shape[0] // 1024 * 1024 * args.epochs,
                                                      float(np.mean([i["train_ms"] for i in infos]))),
         "roofline": {"kernel": f"{kname} (plain OMP pass, N=100000)", "bound": "alu",
-                     "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s", "frac": achieved / 157.3,
+                     "achieved": achieved, "peak": FP32_PEAK, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK,
                      "traffic": measured_traffic(kname), "traffic_unit": "bytes per launch (HBM read + write)",
-                     "per_signal_flops": f_sig,
-                     "per_signal_bytes": omp_bytes_per_signal(64, 8)},
+                     "per_signal_flops": f_sig, "flops_note": ALGO_FLOPS_NOTE,
+                     "alu_ops_per_signal": omp_alu_ops_per_signal(256, 8),
+                     "per_signal_bytes": omp_bytes_per_signal(64, 8),
+                     "kernel_ms": kms,
+                     "mix_ceiling": {"peak": omp_mix_ceiling(64, 256, 8), "frac": achieved / omp_mix_ceiling(64, 256, 8),
+                                     "unit": "TFLOP/s",
+                                     "derivation": "correlations (2mK flops) at the 157.3 TFLOP/s FP32 matrix-core "
+                                                   "peak, the other flops at 78.6 TFLOP/s (FP32 vector issue "
+                                                   "without packed FP32), combined harmonically"}},
     }
     eq = [c for c in curve if c["rmse_ratio"] <= 1.01]
     if eq:

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_1403_4781_amd import synth
-from tests.parity import compare, rmse, to_np
+from tests.parity import compare, correlation_network, proposer_parity, rmse, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -105,28 +105,22 @@ def test_proposed_coding_large(h, dev):
     assert (np.diff(cn, axis=1) > 0).all() and cn.min() >= 0 and cn.max() < 1024
     for n in range(400):
         assert set(gi[n, :gn[n]]) <= set(cn[n])
-    print("case proposed large parity", flush=True)
+    print("case proposed large parity, random network", flush=True)
     plain = oracle.omp(D, Y, 16)
     eps_fb = 1.1 * float(np.sqrt(np.mean(plain.res_norm ** 2)))
-    X, fb, nfb, cand = h.omp_code_proposed(p, Dt, Yt, 16, 48, eps_fb, want_cand=True)
-    lg = oracle.mlp_forward(Ws, bs, Y)
-    ora = oracle.propose_code(D, Y, lg, 48, 16, eps_fb)
-    srt = -np.sort(-lg, axis=1)
-    boundary = (srt[:, 47] - srt[:, 48]) < 1e-3 * np.maximum(np.abs(srt[:, 47]), 1.0)
-    cn = cand.cpu().numpy()
-    same_c = (cn == ora.cand).all(axis=1)
-    print(f"  candidates agree {same_c[~boundary].mean():.5f} fallbacks gpu {nfb} oracle {int(ora.fell_back.sum())}",
-          flush=True)
-    assert same_c[~boundary].mean() >= 0.999
-    fbg = fb.cpu().numpy().astype(bool)
-    ok = same_c & (fbg == ora.fell_back.astype(bool))
-    assert ok.mean() >= 0.99
-    gi, gc, gn = to_np(X)
-    agree = ok & (gn == ora.nnz) & (np.where(np.arange(16)[None] < gn[:, None], gi, -1) ==
-                                    np.where(np.arange(16)[None] < ora.nnz[:, None], ora.idx, -1)).all(axis=1)
-    print(f"  code agreement {agree[ok].mean():.5f}", flush=True)
-    assert agree[ok].mean() >= 0.99
+    proposer_parity(h, dev, p, D, Y, 16, 48, eps_fb, Ws, bs, "proposed K1024 random net")
     p.close()
+    # the correlation network (logits |d_k^T y| / ||y||): restricted codes survive for a share
+    Wc, bc = correlation_network(D)
+    p = h.proposer(Wc, bc)
+    kept = []
+    for mult in (1.1, 5.0):
+        print(f"case proposed large parity, correlation network, threshold x{mult}", flush=True)
+        out = proposer_parity(h, dev, p, D, Y, 16, 48, mult * eps_fb, Wc, bc, f"proposed K1024 corr x{mult}")
+        kept.append(out["restricted"])
+    p.close()
+    print(f"  restricted codes kept: {kept}", flush=True)
+    assert max(kept) >= 40
 
 
 def test_split_merge_large_reduced(h, dev):
