@@ -96,6 +96,22 @@ smdl_status smdl_gram(smdl_t h, const float* D, int m, int K, float* G);
 smdl_status smdl_omp_code(smdl_t h, const float* D, int m, int K, const float* Y, int64_t N,
                           int s_max, float eps, smdl_codes X, float* res_norm);
 
+/*
+ * smdl_omp_code for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same coding, the same arguments and
+ * results, but no allocation of any kind.  Its scratch memory (packed dictionary, Gram matrix,
+ * launch descriptors: 5 MiB + 4 KiB, enough for the library's largest dictionary, m <= 256 and
+ * K <= 1024) is one fixed array per GPU, held until the process ends; its address is taken when
+ * a handle is created on that GPU.  Larger shapes return SMDL_E_SHAPE.  The tile is the
+ * handle's current choice for the shape (smdl_tune / smdl_set_tile, or the default); nothing is
+ * autotuned here.  All calls on one GPU share the array: calls that overlap on one GPU (two
+ * threads, two streams) race and must be serialised by the caller.  Each call rewrites every
+ * part of the scratch it reads.  While the handle's stream is being captured into a HIP graph
+ * the call only records its work (no synchronisation); otherwise it returns when it is done.
+ */
+smdl_status smdl_omp_code_noalloc(smdl_t h, const float* D, int m, int K, const float* Y, int64_t N,
+                                  int s_max, float eps, smdl_codes X, float* res_norm);
+
 /* ---------------------------------------------------------------------------------------- */
 /* Dictionary update                                                                        */
 /* ---------------------------------------------------------------------------------------- */

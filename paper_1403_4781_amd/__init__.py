@@ -71,6 +71,7 @@ def _load():
         "smdl_version": [],
         "smdl_gram": [vp, vp, i32, i32, vp],
         "smdl_omp_code": [vp, vp, i32, i32, vp, i64, i32, f32, _Codes, vp],
+        "smdl_omp_code_noalloc": [vp, vp, i32, i32, vp, i64, i32, f32, _Codes, vp],
         "smdl_mod_update": [vp, vp, i32, i64, _Codes, i32, vp, C.POINTER(C.c_int32)],
         "smdl_learn": [vp, vp, i32, i64, i32, i32, i32, vp, _Codes],
         "smdl_learn_init": [vp, vp, i32, i64, i32, i32, i32, vp, vp, _Codes],

@@ -79,6 +79,10 @@ extern "C" smdl_status smdl_create(smdl_t* out, int device, void* stream) {
             delete h;
             return SMDL_E_HIP;
         }
+    if (noalloc_setup(h) != SMDL_OK) {
+        smdl_destroy(h);
+        return SMDL_E_HIP;
+    }
     *out = h;
     return SMDL_OK;
 }

@@ -124,6 +124,9 @@ struct ModPlan {
 };
 
 smdl_status check_dims(smdl_t h, int m, int K, int s);
+// Take the device address of this device's fixed scratch array (the allocation-free coding
+// entry point); called once per handle at creation, with the handle's device current.
+smdl_status noalloc_setup(smdl_t h);
 // SMDL_E_NUMERIC if any of the n floats at x (device) is not finite (synchronises the stream).
 smdl_status check_finite(smdl_t h, const float* x, int64_t n, const char* what);
 smdl_status check_codes(smdl_t h, const smdl_codes& X, int64_t N, int s_needed);
