@@ -100,7 +100,7 @@ smdl_status smdl_omp_code(smdl_t h, const float* D, int m, int K, const float* Y
  * smdl_omp_code for callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): the same coding, the same arguments and
  * results, but no allocation of any kind.  Its scratch memory (packed dictionary, Gram matrix,
- * launch descriptors: 5 MiB + 4 KiB, enough for the library's largest dictionary, m <= 256 and
+ * launch descriptors: 6 MiB + 8 KiB, enough for the library's largest dictionary, m <= 256 and
  * K <= 1024) is one fixed array per GPU, held until the process ends; its address is taken when
  * a handle is created on that GPU.  Larger shapes return SMDL_E_SHAPE.  The tile is the
  * handle's current choice for the shape (smdl_tune / smdl_set_tile, or the default); nothing is

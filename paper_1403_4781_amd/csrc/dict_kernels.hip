@@ -33,6 +33,48 @@ __global__ void pack_dict_kernel(const PackDesc* __restrict__ pd, int m, int mch
     }
 }
 
+// Exponent of every atom for the FP16 split: max_r |D[r][k]| * 2^-aexp[k] in [0.5, 1) (0 for a
+// zero atom and for the padding atoms).  One thread per atom, grid.y = dictionary.
+__global__ void atom_exp_kernel(const PackDesc* __restrict__ pd, int m) {
+    const PackDesc p = pd[blockIdx.y];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= p.Kpad) return;
+    float mx = 0.f;
+    if (k < p.K) {
+        const float* col = p.D + (int64_t)k * m;
+        for (int r = 0; r < m; ++r) mx = fmaxf(mx, fabsf(col[r]));
+    }
+    int e = 0;
+    if (mx > 0.f) (void)frexpf(mx, &e);
+    p.aexp[k] = e;
+}
+
+// The FP16 split fragments (layout at OmpDesc).  One thread per lane quadruple.
+__global__ void pack_f16_kernel(const PackDesc* __restrict__ pd, int m, int kblocks) {
+    const PackDesc p = pd[blockIdx.y];
+    const int NRB = p.Kpad >> 4;
+    const int64_t total = (int64_t)kblocks * NRB * 64;
+    _Float16* hi = static_cast<_Float16*>(p.fhi);
+    _Float16* lo = static_cast<_Float16*>(p.flo);
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total;
+         f += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(f & 63);
+        const int64_t r = f >> 6;
+        const int b = (int)(r % NRB);
+        const int kb = (int)(r / NRB);
+        const int atom = 16 * b + (l & 15);
+        const int row0 = 16 * kb + 4 * (l >> 4);
+        const int e = p.aexp[atom];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float v = (atom < p.K && row0 + j < m) ? ldexpf(p.D[(int64_t)atom * m + row0 + j], -e) : 0.f;
+            const _Float16 h = (_Float16)v;
+            hi[4 * f + j] = h;
+            lo[4 * f + j] = (_Float16)(v - (float)h);
+        }
+    }
+}
+
 // G = D^T D for every dictionary.  Block = 4 waves = one 64 x 64 tile of G; wave w computes
 // the 16 x 64 strip of rows 16*(4*tr + w), using the packed fragments for both operands
 // (the B operand of the 16x16x4 MFMA wants D[atom j][row k] in lane j + 16*(k/4 ...) exactly
@@ -264,6 +306,16 @@ hipError_t launch_pack_dict_m(const void* dev_pack_desc, int n_dict, int max_kpa
     dim3 grid(grid_for(total, 256), n_dict);
     hipLaunchKernelGGL(pack_dict_kernel, grid, dim3(256), 0, st,
                        static_cast<const PackDesc*>(dev_pack_desc), m, mchunks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(atom_exp_kernel, dim3((max_kpad + 255) / 256, n_dict), dim3(256), 0, st,
+                       static_cast<const PackDesc*>(dev_pack_desc), m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the split covers every 64-row chunk (mpad rows): the 16-row blocks past m are zero
+    const int kblocks = mchunks * 4;
+    const int64_t t16 = (int64_t)kblocks * (max_kpad / 16) * 64;
+    hipLaunchKernelGGL(pack_f16_kernel, dim3(grid_for(t16, 256), n_dict), dim3(256), 0, st,
+                       static_cast<const PackDesc*>(dev_pack_desc), m, kblocks);
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ def main(nunits: int = 8):
             f.write("// Generated instantiations of the fused OMP kernel (see omp_kernel.h).\n")
             f.write('#include "omp_kernel.h"\n\nnamespace smdl_omp {\n')
             for EM, SM, G, TT in lst:
-                f.write(f"template hipError_t launch_one<{EM}, {SM}, {G}, {TT}>(const OmpArgs&, int, hipStream_t, int);\n")
+                f.write(f"template hipError_t launch_one<{EM}, {SM}, {G}, {TT}>(const OmpArgs&, int, int, hipStream_t);\n")
             f.write("}  // namespace smdl_omp\n")
     with open(os.path.join(HERE, "omp_table.inc"), "w") as f:
         f.write("// Generated: instantiated (EM, SM, G, TT) tiles of the fused OMP kernel.\n")

@@ -10,12 +10,16 @@
 
 namespace {
 
-// Layout of the scratch array: the launch descriptors first, then the packed fragments
-// (mpad x Kpad floats), then the Gram matrix (Kpad rows of gld floats).
+// Layout of the scratch array: the launch descriptors (and the work counter) and the atom
+// exponents first, then the
+// packed fragments (mpad x Kpad floats), their FP16 split (hi and lo, mpad x Kpad halves each),
+// then the Gram matrix (Kpad rows of gld floats).
 constexpr size_t DESC_BYTES = 4096;
+constexpr size_t AEXP_BYTES = (size_t)SMDL_MAX_K * 4;                  // 4 KiB
 constexpr size_t FRAG_BYTES = (size_t)SMDL_MAX_M * SMDL_MAX_K * 4;     // 1 MiB
+constexpr size_t F16_BYTES = (size_t)SMDL_MAX_M * SMDL_MAX_K * 2 * 2;  // 1 MiB
 constexpr size_t GRAM_BYTES = (size_t)SMDL_MAX_K * SMDL_MAX_K * 4;     // 4 MiB (gld <= 1024)
-constexpr size_t SCRATCH_BYTES = DESC_BYTES + FRAG_BYTES + GRAM_BYTES;
+constexpr size_t SCRATCH_BYTES = DESC_BYTES + AEXP_BYTES + FRAG_BYTES + F16_BYTES + GRAM_BYTES;
 
 __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
@@ -27,7 +31,7 @@ struct Descs {
     GramDesc gd;
     OmpDesc od;
 };
-static_assert(sizeof(Descs) <= DESC_BYTES, "descriptor block too large");
+static_assert(sizeof(Descs) <= DESC_BYTES / 2, "descriptor block too large");
 
 // The descriptors come in as kernel arguments and are stored into the scratch array, so that no
 // host-to-device copy is queued.
@@ -69,17 +73,21 @@ extern "C" smdl_status smdl_omp_code_noalloc(smdl_t h, const float* D, int m, in
     (void)hipSetDevice(h->device);
     unsigned char* base = static_cast<unsigned char*>(g_scratch[h->device]);
     Descs* dd = reinterpret_cast<Descs*>(base);
-    float4* frag = reinterpret_cast<float4*>(base + DESC_BYTES);
-    float* gram = reinterpret_cast<float*>(base + DESC_BYTES + FRAG_BYTES);
+    int* queue = reinterpret_cast<int*>(base + DESC_BYTES / 2);   // work counter (zeroed by the launch)
+    int32_t* aexp = reinterpret_cast<int32_t*>(base + DESC_BYTES);
+    float4* frag = reinterpret_cast<float4*>(base + DESC_BYTES + AEXP_BYTES);
+    uint16_t* fhi = reinterpret_cast<uint16_t*>(base + DESC_BYTES + AEXP_BYTES + FRAG_BYTES);
+    uint16_t* flo = fhi + (size_t)mpad * Kpad;
+    float* gram = reinterpret_cast<float*>(base + DESC_BYTES + AEXP_BYTES + FRAG_BYTES + F16_BYTES);
 
     const OmpTile tile = choose_tile(h, Kpad, s_max, false);
     if (!omp_tile_supported(tile, Kpad, s_max)) return h->fail(SMDL_E_UNSUPPORTED, "no OMP tile for this shape");
     const int T = 16 * tile.tt;
     Descs v;
     std::memset(&v, 0, sizeof(v));
-    v.pd = PackDesc{D, frag, K, Kpad};
+    v.pd = PackDesc{D, frag, fhi, flo, aexp, K, Kpad};
     v.gd = GramDesc{frag, gram, Kpad, gld};
-    v.od = OmpDesc{frag, gram, Y, N, 0, K, Kpad, s_max, gld};
+    v.od = OmpDesc{frag, fhi, flo, aexp, gram, Y, N, 0, K, Kpad, s_max, gld};
     hipError_t e;
     hipLaunchKernelGGL(store_descs_kernel, dim3(1), dim3(64), 0, h->stream, v, dd);
     if ((e = hipGetLastError()) != hipSuccess) return h->hip(e, "descriptors");
@@ -89,6 +97,9 @@ extern "C" smdl_status smdl_omp_code_noalloc(smdl_t h, const float* D, int m, in
     a.desc = &dd->od;
     a.items = nullptr;
     a.n_items = (int)((N + T - 1) / T);
+    a.queue = queue;
+    a.max_kpad = Kpad;
+    a.y_lds = omp_y_lds(tile, Kpad, s_max, m, &Y, 1) ? 1 : 0;
     a.m = m;
     a.mchunks = mpad / 64;
     a.eps2 = eps > 0.f ? eps * eps : 0.f;
@@ -99,7 +110,7 @@ extern "C" smdl_status smdl_omp_code_noalloc(smdl_t h, const float* D, int m, in
     a.nnz = X.nnz;
     a.res = res_norm;
     a.s_out = X.s_max;
-    if ((e = launch_omp(tile, Kpad, s_max, a, a.n_items, h->stream)) != hipSuccess) return h->hip(e, "omp launch");
+    if ((e = launch_omp(tile, Kpad, s_max, a, a.n_items, h->n_cu, h->stream)) != hipSuccess) return h->hip(e, "omp launch");
     // under graph capture the work is only recorded; otherwise the call returns when it is done
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if ((e = hipStreamIsCapturing(h->stream, &cap)) != hipSuccess) return h->hip(e, "capture status");

@@ -2,14 +2,14 @@
 #include "omp_kernel.h"
 
 namespace smdl_omp {
-template hipError_t launch_one<4, 12, 16, 2>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<8, 12, 16, 1>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<12, 8, 16, 4>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<16, 8, 16, 2>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<4, 12, 32, 1>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<8, 8, 32, 4>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<16, 8, 32, 2>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<4, 8, 64, 1>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<4, 16, 64, 4>(const OmpArgs&, int, hipStream_t, int);
-template hipError_t launch_one<8, 16, 64, 2>(const OmpArgs&, int, hipStream_t, int);
+template hipError_t launch_one<4, 12, 16, 2>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<8, 12, 16, 1>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<12, 8, 16, 4>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<16, 8, 16, 2>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<4, 12, 32, 1>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<8, 8, 32, 4>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<16, 8, 32, 2>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<4, 8, 64, 1>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<4, 16, 64, 4>(const OmpArgs&, int, int, hipStream_t);
+template hipError_t launch_one<8, 16, 64, 2>(const OmpArgs&, int, int, hipStream_t);
 }  // namespace smdl_omp

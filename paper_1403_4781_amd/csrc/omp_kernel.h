@@ -2,9 +2,11 @@
 //
 // One work item = up to T = 16*TT signals coded against one dictionary.
 //
-// Phase A (matrix cores): alpha0 = D^T y for the T signals with v_mfma_f32_16x16x4f32,
-//   A operand = packed dictionary fragments (coalesced float4 loads, L2 resident),
-//   B operand = the signals (float4 loads straight from HBM).  alpha0 and ||y||^2 go to LDS.
+// Phase A (matrix cores): alpha0 = D^T y for the T signals on v_mfma_f32_16x16x16_f16 from a
+//   three-term FP16 split of both operands (FP32-accurate to about 2^-22; see the phase),
+//   A operand = split dictionary fragments (coalesced 8-byte loads, L2 resident),
+//   B operand = the signals (float4 loads straight from HBM, split in registers).  alpha0 and
+//   ||y||^2 go to LDS.
 // Phase B (vector ALU): every signal is handled by a group of G lanes (16, 32 or 64); lane g
 //   owns the E = Kpad/G correlation entries e(g,t) = 4G*(t/4) + 4g + t%4.  Per step k:
 //     j     = argmax_e |c_e|                (lane-local scan + butterfly over the group)
@@ -20,6 +22,7 @@
 //   computed in correlation space; U (K x k), c and the Cholesky data stay in registers.
 #pragma once
 
+#include <algorithm>
 #include <utility>
 
 #include "smdl_internal.h"
@@ -252,9 +255,207 @@ __device__ __forceinline__ void run_steps(State<EM, SM>& st, const StepCtx& x,
     (void)(omp_step<KKs, EM, SM, G>(st, x) && ...);
 }
 
+// The work item with index `item`: from the item list, or the item-th block of T signals of the
+// single descriptor (of the device-side count in gather mode).
+template <int T>
+__device__ __forceinline__ OmpItem item_of(const OmpArgs& a, int item) {
+    if (a.items) return a.items[item];
+    OmpItem it;
+    it.desc = 0;
+    it.first = (int64_t)item * T;
+    const int64_t n = a.list_count ? (int64_t)*a.list_count : a.desc[0].n;
+    const int64_t left = n - it.first;
+    it.count = (int)(left < T ? left : T);
+    return it;
+}
+
+// A copy of a struct held in LDS, every 32-bit word read as a wave-uniform value (so that its
+// pointers and sizes live in scalar registers).
+template <typename S>
+__device__ __forceinline__ S uniform_copy(const S& src) {
+    static_assert(sizeof(S) % 4 == 0, "word-sized struct expected");
+    constexpr int W = sizeof(S) / 4;
+    uint32_t w[W];
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(&src);
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)p[i]);
+    S out;
+    __builtin_memcpy(&out, w, sizeof(S));
+    return out;
+}
+
+// Direct-to-LDS copy of the item's signals, issued by one wave.  Layout: rows 4q .. 4q + 3 of the
+// signal in slot s at ybuf + 4 (q T + s), so that the 16 lanes reading one row group of 16
+// signals read 256 contiguous bytes.  Lane l of an instruction writes LDS address (instruction
+// base) + 16 l, so every instruction fills 64 consecutive positions; each lane fetches the chunk
+// its position holds (nothing for the slots past the item's count).
+template <int T>
+__device__ __forceinline__ void prefetch_signals(const OmpArgs& a, const OmpItem& it, const float* Y, float* ybuf,
+                                                 int lane) {
+    const int total = (a.m >> 2) * T;
+    for (int base = 0; base < total; base += 64) {
+        const int p = base + lane;
+        const int sl = p % T, q = p / T;
+        if (p < total && sl < it.count) {
+            int64_t sig = it.first + sl;
+            if (a.sig_list) sig = a.sig_list[sig];
+            __builtin_amdgcn_global_load_lds(
+                (const void __attribute__((address_space(1)))*)(Y + sig * (int64_t)a.m + 4 * q),
+                (void __attribute__((address_space(3)))*)(ybuf + 4 * base), 16, 0, 0);
+        }
+    }
+}
+
+// Phase A of one work item: alpha0 and ||y||^2 of its signals into LDS (see the kernel).  LDS: the
+// signals come from the item's copy in LDS (m % 4 == 0), otherwise from memory.
+template <int TT, int RBW, bool LDS>
+__device__ __forceinline__ void alpha0_phase(const OmpArgs& a, const OmpDesc& d, const OmpItem& it,
+                                             const float* ybuf, float* alpha, float* yn2, int stride, int lane,
+                                             int wave) {
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    const int Kpad = d.Kpad;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int NRB = Kpad >> 4;
+    const int rbw = NRB >> 2;          // row blocks of this wave (Kpad % 64 == 0)
+    const int rb0 = wave * rbw;
+    const int KB = 4 * a.mchunks;      // 16-row blocks (rows past m are zero)
+    const bool vec = ((a.m & 3) == 0) && ((reinterpret_cast<uintptr_t>(d.Y) & 15) == 0);
+    const float* yp[TT];
+    bool yok[TT];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+        const int sl = 16 * tt + i16;
+        yok[tt] = sl < it.count;
+        int64_t sig = it.first + sl;
+        if (a.sig_list) sig = yok[tt] ? a.sig_list[sig] : 0;
+        yp[tt] = d.Y + (yok[tt] ? sig : 0) * (int64_t)a.m;
+    }
+    // four rows of signal 16 tt + i16 (zero past m and for empty slots): from the LDS copy
+    // (an in-bounds read whatever the slot, then a select), or from memory
+    auto yrow = [&](int tt, int r) -> float4 {
+        if (LDS) {
+            const float4 v = *reinterpret_cast<const float4*>(ybuf + 4 * ((min(r, a.m - 4) >> 2) * (16 * TT) + 16 * tt + i16));
+            const bool ok = yok[tt] && r < a.m;
+            return ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        return yok[tt] ? load_y4(yp[tt], r, a.m, vec) : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    const h4* fhi = static_cast<const h4*>(d.fhi);
+    const h4* flo = static_cast<const h4*>(d.flo);
+    // the scale of each signal: none when its largest entry lies in [2^-3, 2^14) (no FP16
+    // overflow, the lo halves of the largest entries are normal FP16 numbers), otherwise the
+    // power of two that brings it into [0.5, 1)
+    int ye[TT];
+    float ysq[TT];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+        float mx = 0.f;
+        for (int kb = 0; kb < KB; ++kb) {
+            const float4 v = yrow(tt, 16 * kb + 4 * kq);
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+        mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+        int e = 0;
+        if (mx > 0.f) (void)frexpf(mx, &e);
+        ye[tt] = (mx == 0.f || (mx >= 0.125f && mx < 16384.f)) ? 0 : e;
+        ysq[tt] = 0.f;
+    }
+    // The products over all 16-row blocks, with ||y||^2.  The fragments of all row blocks of a
+    // 16-row block are requested together, those of the next block while the current one is
+    // multiplied (row blocks past this wave's share are clamped to its last one, not used).
+    f32x4 acc[RBW][TT];
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+        for (int tt = 0; tt < TT; ++tt) acc[rb][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    h4 nh[RBW], nl[RBW];
+    auto request = [&](int kb) {
+#pragma unroll
+        for (int rb = 0; rb < RBW; ++rb) {
+            const size_t o = ((size_t)kb * NRB + rb0 + min(rb, rbw - 1)) * 64 + lane;
+            nh[rb] = fhi[o];
+            nl[rb] = flo[o];
+        }
+    };
+    // (wide waves, RBW > 4, request each block's fragments just before its products: the second
+    // register set would not fit beside the accumulators)
+    constexpr bool AHEAD = RBW <= 4;
+    if (AHEAD) request(0);
+    for (int kb = 0; kb < KB; ++kb) {
+        const int r = 16 * kb + 4 * kq;
+        if (!AHEAD) request(kb);
+        h4 ah[RBW], al[RBW];
+#pragma unroll
+        for (int rb = 0; rb < RBW; ++rb) {
+            ah[rb] = nh[rb];
+            al[rb] = nl[rb];
+        }
+        if (AHEAD && kb + 1 < KB) request(kb + 1);
+        h4 bh[TT], bl[TT];
+#pragma unroll
+        for (int tt = 0; tt < TT; ++tt) {
+            float4 v = yrow(tt, r);
+            ysq[tt] += v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+            v.x = ldexpf(v.x, -ye[tt]);
+            v.y = ldexpf(v.y, -ye[tt]);
+            v.z = ldexpf(v.z, -ye[tt]);
+            v.w = ldexpf(v.w, -ye[tt]);
+            bh[tt][0] = (_Float16)v.x;
+            bh[tt][1] = (_Float16)v.y;
+            bh[tt][2] = (_Float16)v.z;
+            bh[tt][3] = (_Float16)v.w;
+            bl[tt][0] = (_Float16)(v.x - (float)bh[tt][0]);
+            bl[tt][1] = (_Float16)(v.y - (float)bh[tt][1]);
+            bl[tt][2] = (_Float16)(v.z - (float)bh[tt][2]);
+            bl[tt][3] = (_Float16)(v.w - (float)bh[tt][3]);
+        }
+#pragma unroll
+        for (int rb = 0; rb < RBW; ++rb) {
+            if (rb < rbw) {
+#pragma unroll
+                for (int tt = 0; tt < TT; ++tt) {
+                    acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(al[rb], bh[tt], acc[rb][tt], 0, 0, 0);
+                    acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[rb], bl[tt], acc[rb][tt], 0, 0, 0);
+                    acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[rb], bh[tt], acc[rb][tt], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D[i][j] of the 16x16 tile sits in lane j + 16*(i/4), register i%4:
+    // row i = atom 16*rb + 4*kq + q, column j = signal i16.  Undo the scales.
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb) {
+        if (rb < rbw) {
+            const int atom0 = 16 * (rb0 + rb) + 4 * kq;
+            const int4 ea = *reinterpret_cast<const int4*>(d.aexp + atom0);
+#pragma unroll
+            for (int tt = 0; tt < TT; ++tt) {
+                float* dst = alpha + (16 * tt + i16) * stride + atom0;
+                *reinterpret_cast<float4*>(dst) =
+                    make_float4(ldexpf(acc[rb][tt][0], ea.x + ye[tt]), ldexpf(acc[rb][tt][1], ea.y + ye[tt]),
+                                ldexpf(acc[rb][tt][2], ea.z + ye[tt]), ldexpf(acc[rb][tt][3], ea.w + ye[tt]));
+            }
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+        float v = ysq[tt];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (wave == 0 && kq == 0) yn2[16 * tt + i16] = v;
+    }
+}
+
 // Two waves per SIMD (at most 256 registers per lane), except where a lane holds 16 x 16 or more
 // directions: those tiles get one wave per SIMD, so that the AGPRs can hold what does not fit in
 // the 256 VGPRs (no scratch: measured 2x faster at K=1024, s=16 than the spilling two-wave build).
+//
+// Persistent: work group b takes the items b, b + grid, b + 2 grid, ... .  Each item's work
+// item and dictionary descriptor are staged in LDS one item ahead (so an item starts without a
+// chain of dependent memory round trips), and with a.y_lds the next item's signals are copied
+// into the other half of a double buffer in LDS while the current item runs its greedy loop, so
+// that the correlations of the next item read LDS instead of waiting on HBM.
 template <int EM, int SM, int G, int TT>
 __global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpArgs a) {
     constexpr int T = 16 * TT;
@@ -264,133 +465,64 @@ __global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpAr
     constexpr int RBW = EM * G / 64;     // max 16-atom row blocks per wave in phase A
 
     extern __shared__ float lds[];
-    __shared__ int s_item;
-    __shared__ OmpItem s_it;
+    __shared__ OmpItem s_it[2];
+    __shared__ OmpDesc s_desc[2];
 
     const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // fixed LDS layout for every item: alpha0 rows of the widest dictionary, ||y||^2, signals
+    float* const yn2 = lds + T * (a.max_kpad + 4);
+    float* const ybuf0 = yn2 + T;
+    const bool y_lds = a.y_lds != 0;
 
     int n_items = a.n_items;
     if (a.list_count) n_items = (*a.list_count + T - 1) / T;
+    int item = blockIdx.x;
+    if (item >= n_items) return;
+    if (tid == 0) {
+        s_it[0] = item_of<T>(a, item);
+        s_desc[0] = a.desc[s_it[0].desc];
+    }
+    __syncthreads();
+    if (y_lds && wave == 0) prefetch_signals<T>(a, s_it[0], s_desc[0].Y, ybuf0, tid & 63);
 
-    for (int round = 0;; ++round) {
-        int item;
-        if (a.queue) {
-            if (tid == 0) s_item = atomicAdd(a.queue, 1);
-            __syncthreads();
-            item = s_item;
-        } else {
-            item = round == 0 ? (int)blockIdx.x : 0x7fffffff;
-        }
-        if (item >= n_items) break;
-        if (tid == 0) {
-            if (a.items) {
-                s_it = a.items[item];
-            } else {
-                OmpItem it;
-                it.desc = 0;
-                it.first = (int64_t)item * T;
-                int64_t n = a.list_count ? (int64_t)*a.list_count : a.desc[0].n;
-                int64_t left = n - it.first;
-                it.count = (int)(left < T ? left : T);
-                s_it = it;
-            }
-        }
+    for (int cur = 0;; cur ^= 1) {
+        if (y_lds) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's signal copy has landed
         __syncthreads();
-        // the item is the same for the whole group: keep it (and so the descriptor) in SGPRs
-        OmpItem it;
-        it.desc = __builtin_amdgcn_readfirstlane(s_it.desc);
-        it.count = __builtin_amdgcn_readfirstlane(s_it.count);
-        it.first = ((int64_t)__builtin_amdgcn_readfirstlane((int)(s_it.first >> 32)) << 32) |
-                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)s_it.first);
-        const OmpDesc d = a.desc[it.desc];
+        // the item and its descriptor are the same for the whole group: keep them in SGPRs
+        const OmpItem it = uniform_copy(s_it[cur]);
+        const OmpDesc d = uniform_copy(s_desc[cur]);
+        const int next = item + (int)gridDim.x;
+        // the next item, requested now so that its round trips overlap phase A
+        OmpItem itn{};
+        if (tid == 0 && next < n_items) itn = item_of<T>(a, next);
         // lane ids made opaque per item: otherwise the compiler hoists every lane-dependent
         // address of both phases out of the item loop and keeps them all live in registers
         int lid = tid & 63;
         asm volatile("" : "+v"(lid));
         const int lane = lid;
-        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
         const int Kpad = d.Kpad;
         const int stride = Kpad + 4;           // LDS row stride (floats) of alpha0
         float* alpha = lds;                    // T x stride
-        float* yn2 = lds + T * stride;         // T
+        const float* ybuf = ybuf0 + cur * T * a.m;
 
         // ------------------------------------------------------------------ phase A
-        {
-            const int i16 = lane & 15, kq = lane >> 4;
-            const int NRB = Kpad >> 4;
-            const int rbw = NRB >> 2;          // row blocks of this wave (Kpad % 64 == 0)
-            const int rb0 = wave * rbw;
-            f32x4 acc[RBW][TT];
-#pragma unroll
-            for (int rb = 0; rb < RBW; ++rb)
-#pragma unroll
-                for (int tt = 0; tt < TT; ++tt) acc[rb][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
-            const bool vec = ((a.m & 3) == 0) && ((reinterpret_cast<uintptr_t>(d.Y) & 15) == 0);
-            const float* yp[TT];
-            bool yok[TT];
-#pragma unroll
-            for (int tt = 0; tt < TT; ++tt) {
-                int sl = 16 * tt + i16;
-                yok[tt] = sl < it.count;
-                int64_t sig = it.first + sl;
-                if (a.sig_list) sig = yok[tt] ? a.sig_list[sig] : 0;
-                yp[tt] = d.Y + (yok[tt] ? sig : 0) * (int64_t)a.m;
-            }
-            float ysq[TT];
-#pragma unroll
-            for (int tt = 0; tt < TT; ++tt) ysq[tt] = 0.f;
-            for (int c = 0; c < a.mchunks; ++c) {
-                float4 yv[TT][4];
-#pragma unroll
-                for (int tt = 0; tt < TT; ++tt)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int r = 64 * c + 16 * kq + 4 * q;
-                        yv[tt][q] = yok[tt] ? load_y4(yp[tt], r, a.m, vec) : make_float4(0.f, 0.f, 0.f, 0.f);
-                        ysq[tt] += yv[tt][q].x * yv[tt][q].x + yv[tt][q].y * yv[tt][q].y +
-                                   yv[tt][q].z * yv[tt][q].z + yv[tt][q].w * yv[tt][q].w;
-                    }
-#pragma unroll
-                for (int rb = 0; rb < RBW; ++rb) {
-                    if (rb < rbw) {
-                        const float4* fp = d.dfrag + ((size_t)(c * NRB + rb0 + rb) * 4) * 64 + lane;
-                        float4 af[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) af[q] = fp[q * 64];
-#pragma unroll
-                        for (int tt = 0; tt < TT; ++tt)
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q].x, yv[tt][q].x, acc[rb][tt], 0, 0, 0);
-                                acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q].y, yv[tt][q].y, acc[rb][tt], 0, 0, 0);
-                                acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q].z, yv[tt][q].z, acc[rb][tt], 0, 0, 0);
-                                acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q].w, yv[tt][q].w, acc[rb][tt], 0, 0, 0);
-                            }
-                    }
-                }
-            }
-            // D[i][j] of the 16x16 tile sits in lane j + 16*(i/4), register i%4:
-            // row i = atom 16*rb + 4*kq + q, column j = signal i16.
-#pragma unroll
-            for (int rb = 0; rb < RBW; ++rb) {
-                if (rb < rbw) {
-#pragma unroll
-                    for (int tt = 0; tt < TT; ++tt) {
-                        float* dst = alpha + (16 * tt + i16) * stride + 16 * (rb0 + rb) + 4 * kq;
-                        *reinterpret_cast<float4*>(dst) =
-                            make_float4(acc[rb][tt][0], acc[rb][tt][1], acc[rb][tt][2], acc[rb][tt][3]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int tt = 0; tt < TT; ++tt) {
-                float v = ysq[tt];
-                v += __shfl_xor(v, 16, 64);
-                v += __shfl_xor(v, 32, 64);
-                if (wave == 0 && kq == 0) yn2[16 * tt + i16] = v;
-            }
+        // alpha0 = D^T y on the FP16 matrix cores from a three-term split of both operands
+        // (hi*hi + hi*lo + lo*hi, FP32 accumulation).  Each atom is scaled by a power of two
+        // (exact) so that its largest entry lies in [0.5, 1), and so is each signal whose largest
+        // entry lies outside [2^-3, 2^14); both halves then stay in the FP16 range, the products
+        // carry about 22 significant bits and the dropped lo*lo term lies below 2^-22 of the
+        // largest product.  The scales are undone on the FP32 sums.
+        if (y_lds) alpha0_phase<TT, RBW, true>(a, d, it, ybuf, alpha, yn2, stride, lane, wave);
+        else alpha0_phase<TT, RBW, false>(a, d, it, ybuf, alpha, yn2, stride, lane, wave);
+        // the next item into the other slot (its signals into the other half of the buffer)
+        if (tid == 0 && next < n_items) {
+            s_it[cur ^ 1] = itn;
+            s_desc[cur ^ 1] = a.desc[itn.desc];
         }
         __syncthreads();
+        if (y_lds && wave == 0 && next < n_items)
+            prefetch_signals<T>(a, s_it[cur ^ 1], s_desc[cur ^ 1].Y, ybuf0 + (cur ^ 1) * T * a.m, lane);
 
         // ------------------------------------------------------------------ phase B
         {
@@ -461,25 +593,39 @@ __global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpAr
             }
         }
         __syncthreads();
+        if (next >= n_items) break;
+        item = next;
     }
 }
 
-// Dynamic LDS of one work group: alpha0 (T rows of maxKpad + 4 floats) and ||y||^2 (T floats).
+// Dynamic LDS of one work group: alpha0 (T rows of maxKpad + 4 floats) and ||y||^2 (T floats);
+// with the signal copy (y_lds) also two buffers of T signals of m floats.
 template <int SM, int G, int TT>
-constexpr size_t omp_lds_size(int maxKpad) {
-    return ((size_t)16 * TT * (maxKpad + 4) + 16 * TT) * 4;
+constexpr size_t omp_lds_size(int maxKpad, int m_copy) {
+    return ((size_t)16 * TT * (maxKpad + 4) + 16 * TT + (size_t)2 * 16 * TT * m_copy) * 4;
 }
 
+// Launch with a persistent grid: as many work groups as fit on the device at once (by the
+// occupancy of this instantiation and its LDS), at most one per item.
 template <int EM, int SM, int G, int TT>
-hipError_t launch_one(const OmpArgs& a, int grid, hipStream_t st, int maxKpad) {
-    const size_t lds = omp_lds_size<SM, G, TT>(maxKpad);
+hipError_t launch_one(const OmpArgs& a, int max_items, int n_cu, hipStream_t st) {
+    const size_t lds = omp_lds_size<SM, G, TT>(a.max_kpad, a.y_lds ? a.m : 0);
+    const void* fn = reinterpret_cast<const void*>(&omp_fused<EM, SM, G, TT>);
     static size_t lds_enabled = 64 * 1024;   // dynamic LDS this instantiation may request
+    static size_t occ_lds = 0;               // LDS size the cached occupancy was taken at
+    static int occ = 0;
+    hipError_t e;
     if (lds > lds_enabled) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&omp_fused<EM, SM, G, TT>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+        if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess) return e;
         lds_enabled = lds;
     }
+    if (occ_lds != lds || occ < 1) {
+        int nb = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds)) != hipSuccess) return e;
+        occ = nb < 1 ? 1 : nb;
+        occ_lds = lds;
+    }
+    const int grid = (int)std::min<int64_t>(std::max(max_items, 1), (int64_t)n_cu * occ);
     hipLaunchKernelGGL((omp_fused<EM, SM, G, TT>), dim3(grid), dim3(256), lds, st, a);
     return hipGetLastError();
 }

@@ -588,6 +588,12 @@ extern "C" smdl_status smdl_omp_code_proposed(smdl_t h, smdl_prop_t p, const flo
     oa.n_items = (int)((N + T - 1) / T);
     oa.sig_list = fb_list;
     oa.list_count = fb_cnt;
+    oa.queue = plan.queue;
+    oa.max_kpad = plan.maxKpad;
+    {
+        const float* ys[1] = {Y};
+        oa.y_lds = omp_y_lds(tile, plan.maxKpad, s_max, m, ys, 1) ? 1 : 0;
+    }
     oa.m = m;
     oa.mchunks = plan.mchunks;
     oa.eps2 = 0.f;
@@ -598,7 +604,8 @@ extern "C" smdl_status smdl_omp_code_proposed(smdl_t h, smdl_prop_t p, const flo
     oa.nnz = X.nnz;
     oa.res = nullptr;
     oa.s_out = X.s_max;
-    if ((e = launch_omp(tile, plan.maxKpad, s_max, oa, oa.n_items, h->stream)) != hipSuccess) return h->hip(e, "fallback omp");
+    if ((e = launch_omp(tile, plan.maxKpad, s_max, oa, oa.n_items, h->n_cu, h->stream)) != hipSuccess)
+        return h->hip(e, "fallback omp");
     (void)hipEventRecord(h->ev_prop[3], h->stream);
     int32_t cnt = 0;
     if ((st = h->hip(hipMemcpyAsync(&cnt, fb_cnt, 4, hipMemcpyDeviceToHost, h->stream), "count")) != SMDL_OK) return st;

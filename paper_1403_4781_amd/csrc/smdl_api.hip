@@ -176,7 +176,7 @@ std::vector<OmpTile> candidate_tiles(int Kpad, int s, int lanes_ok) {
         for (int tt : {1, 2, 4}) {
             OmpTile t{lanes, tt};
             if (!(lanes & lanes_ok) || !omp_tile_supported(t, Kpad, s)) continue;
-            if (omp_lds_bytes(t, Kpad, s) > 96 * 1024) continue;
+            if (omp_lds_bytes(t, Kpad, s, 0) > 96 * 1024) continue;
             out.push_back(t);
         }
     return out;
@@ -213,22 +213,30 @@ smdl_status prepare_sets(smdl_t h, int m, std::vector<SetSpec>& sets, const char
         gram_total += (size_t)s.Kpad * gld;
     }
     std::string t(tag);
+    size_t kpad_total = 0;
+    for (auto& s : sets) kpad_total += (size_t)s.Kpad;
     float* frag = (float*)h->ws((t + ".frag").c_str(), frag_total * 4);
     float* gram = (float*)h->ws((t + ".gram").c_str(), gram_total * 4);
-    if (!frag || !gram) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
+    uint16_t* f16 = (uint16_t*)h->ws((t + ".f16").c_str(), frag_total * 2 * 2);   // hi and lo halves
+    int32_t* aexp = (int32_t*)h->ws((t + ".aexp").c_str(), kpad_total * 4);
+    if (!frag || !gram || !f16 || !aexp) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     std::vector<PackDesc> pd(sets.size());
     std::vector<GramDesc> gd(sets.size());
     std::vector<OmpDesc> od(sets.size());
-    size_t fo = 0, go = 0;
+    size_t fo = 0, go = 0, ko = 0;
     for (size_t i = 0; i < sets.size(); ++i) {
         auto& s = sets[i];
         s.frag = reinterpret_cast<float4*>(frag + fo);
         s.gram = gram + go;
+        uint16_t* fhi = f16 + 2 * fo;
+        uint16_t* flo = fhi + (size_t)mpad * s.Kpad;
+        int32_t* ae = aexp + ko;
         fo += (size_t)mpad * s.Kpad;
         go += (size_t)s.Kpad * s.gld;
-        pd[i] = PackDesc{s.D, s.frag, s.K, s.Kpad};
+        ko += (size_t)s.Kpad;
+        pd[i] = PackDesc{s.D, s.frag, fhi, flo, ae, s.K, s.Kpad};
         gd[i] = GramDesc{s.frag, s.gram, s.Kpad, s.gld};
-        od[i] = OmpDesc{s.frag, s.gram, s.Y, s.n, s.out0, s.K, s.Kpad, s.s, s.gld};
+        od[i] = OmpDesc{s.frag, fhi, flo, ae, s.gram, s.Y, s.n, s.out0, s.K, s.Kpad, s.s, s.gld};
     }
     plan.pack_desc = h->ws((t + ".pd").c_str(), pd.size() * sizeof(PackDesc));
     plan.gram_desc = h->ws((t + ".gd").c_str(), gd.size() * sizeof(GramDesc));
@@ -271,6 +279,13 @@ smdl_status build_items(smdl_t h, const std::vector<SetSpec>& sets, int T, const
     return SMDL_OK;
 }
 
+// Whether the OMP launch of `plan` with `tile` can copy the signals into LDS ahead of use.
+static bool plan_y_lds(const CodePlan& plan, OmpTile tile) {
+    std::vector<const float*> ys;
+    for (const auto& d : plan.host_desc) ys.push_back(d.Y);
+    return omp_y_lds(tile, plan.maxKpad, plan.maxS, plan.m, ys.data(), (int)ys.size());
+}
+
 // Queue pack + Gram + OMP for all sets (no host synchronisation; graph-capturable).
 hipError_t enqueue_code(smdl_t h, const CodePlan& plan, OmpTile tile, const CodeOut& out,
                         float eps, bool timed) {
@@ -284,7 +299,9 @@ hipError_t enqueue_code(smdl_t h, const CodePlan& plan, OmpTile tile, const Code
     a.desc = plan.omp_desc;
     a.items = plan.items;
     a.n_items = plan.n_items;
-    a.queue = nullptr;
+    a.queue = plan.queue;
+    a.max_kpad = plan.maxKpad;
+    a.y_lds = plan_y_lds(plan, tile) ? 1 : 0;
     a.m = plan.m;
     a.mchunks = plan.mchunks;
     a.eps2 = eps > 0.f ? eps * eps : 0.f;
@@ -295,15 +312,9 @@ hipError_t enqueue_code(smdl_t h, const CodePlan& plan, OmpTile tile, const Code
     a.nnz = out.nnz;
     a.res = out.res;
     a.s_out = out.s_stride;
-    int grid = plan.n_items;
-    if (plan.persistent) {
-        if ((e = launch_zero_i32(plan.queue, 1, h->stream)) != hipSuccess) return e;
-        a.queue = plan.queue;
-        grid = std::min(plan.n_items, std::max(1, h->n_cu * 2));
-    }
-    if (grid < 1) return hipSuccess;
+    if (plan.n_items < 1) return hipSuccess;
     if (timed) (void)hipEventRecord(h->ev0, h->stream);
-    e = launch_omp(tile, plan.maxKpad, plan.maxS, a, grid, h->stream);
+    e = launch_omp(tile, plan.maxKpad, plan.maxS, a, plan.n_items, h->n_cu, h->stream);
     if (timed) (void)hipEventRecord(h->ev1, h->stream);
     return e;
 }
@@ -367,6 +378,9 @@ smdl_status omp_code_impl(smdl_t h, const float* D, int m, int K, const float* Y
     a.desc = plan.omp_desc;
     a.items = nullptr;
     a.n_items = (int)((sets[0].n + T - 1) / T);
+    a.queue = plan.queue;
+    a.max_kpad = plan.maxKpad;
+    a.y_lds = plan_y_lds(plan, tile) ? 1 : 0;
     a.sig_list = sig_list;
     a.list_count = list_count;
     a.m = m;
@@ -381,7 +395,7 @@ smdl_status omp_code_impl(smdl_t h, const float* D, int m, int K, const float* Y
     a.s_out = X.s_max;
     if (a.n_items < 1) return SMDL_OK;
     (void)hipEventRecord(h->ev0, h->stream);
-    e = launch_omp(tile, plan.maxKpad, s_max, a, a.n_items, h->stream);
+    e = launch_omp(tile, plan.maxKpad, s_max, a, a.n_items, h->n_cu, h->stream);
     (void)hipEventRecord(h->ev1, h->stream);
     if (e != hipSuccess) return h->hip(e, "omp launch");
     h->timed_pending = true;

@@ -36,9 +36,19 @@ inline int gram_ld(int maxKpad) {
     return ld;
 }
 
+// FP16 split fragments of a dictionary for the correlations of the OMP kernel: atom k is scaled by
+// 2^-aexp[k] (aexp[k] = the exponent that brings max_r |D[r][k]| into [0.5, 1); 0 for a zero
+// atom) and split as hi = fp16(v), lo = fp16(v - hi).  For row block kb (16 rows), atom block b
+// (16 atoms) and lane l, the four halves at ((kb * Kpad/16 + b) * 64 + l) * 4 are the rows
+// 16 kb + 4 (l/16) .. + 3 of atom 16 b + l%16: the A operand of v_mfma_f32_16x16x16_f16.
+inline int pad16(int x) { return (x + 15) / 16 * 16; }
+
 // One dictionary and the signals coded against it.
 struct OmpDesc {
     const float4* dfrag;  // packed fragments (mpad x Kpad floats)
+    const void* fhi;      // FP16 split fragments, hi and lo halves (mpad x Kpad halves each)
+    const void* flo;
+    const int32_t* aexp;  // Kpad atom exponents of the split
     const float* gram;    // Kpad rows of gld floats, row-major Gram matrix (zero outside K x K)
     const float* Y;       // signals (m floats each)
     int64_t n;            // number of signals in this set
@@ -57,7 +67,7 @@ struct OmpArgs {
     const OmpDesc* desc;     // descriptors (device)
     const OmpItem* items;    // work items (device); NULL = one descriptor, item i covers T*i..
     int n_items;             // number of items (or, with items == NULL, ceil(n / T))
-    int* queue;              // persistent work counter (device, zeroed before launch) or NULL
+    int* queue;              // unused (the persistent grid strides over the items)
     const int32_t* sig_list; // gather mode: signals to code are sig_list[0 .. *list_count)
     const int32_t* list_count;
     int m, mchunks;
@@ -67,6 +77,9 @@ struct OmpArgs {
     int32_t* nnz;
     float* res;              // optional
     int s_out;               // ELL row stride of the output
+    int max_kpad;            // widest padded dictionary of the launch (LDS layout)
+    int y_lds;               // 1: copy each item's signals into LDS ahead of use (needs m % 4 == 0
+                             // and 16-byte aligned signal arrays; see omp_y_lds)
 };
 
 // Tile configuration of the OMP kernel.
@@ -81,14 +94,23 @@ hipError_t launch_pack_dict_m(const void* dev_pack_desc, int n_dict, int max_kpa
 hipError_t launch_gram_batched(const void* dev_gram_desc, int n_dict, int max_kpad, int mchunks,
                                hipStream_t st);
 bool omp_tile_supported(OmpTile t, int Kpad, int s);
-hipError_t launch_omp(OmpTile t, int maxKpad, int maxS, const OmpArgs& a, int grid,
+// The fused OMP kernel on a persistent grid (work group b takes items b, b + grid, ...).  max_items bounds the
+// number of work items (the exact count may live on the device, a.list_count).
+hipError_t launch_omp(OmpTile t, int maxKpad, int maxS, const OmpArgs& a, int max_items, int n_cu,
                       hipStream_t st);
-size_t omp_lds_bytes(OmpTile t, int maxKpad, int s);
+// LDS of the instantiation serving (t, maxKpad, s) with signal copies of m floats (0: none).
+size_t omp_lds_bytes(OmpTile t, int maxKpad, int s, int m_copy);
+// Whether the signal copies into LDS can be used: m % 4 == 0, every signal array 16-byte aligned
+// and the tile's LDS with the copies within a work group's limit.
+bool omp_y_lds(OmpTile t, int maxKpad, int s, int m, const float* const* Ys, int n_sets);
 
 // Batched dictionary helpers (descriptor arrays live in device memory).
 struct PackDesc {
     const float* D;   // m x K column-major
     float4* dfrag;
+    void* fhi;        // FP16 split fragments (see OmpDesc), mpad x Kpad halves each
+    void* flo;
+    int32_t* aexp;    // Kpad atom exponents
     int K, Kpad;
 };
 struct GramDesc {
