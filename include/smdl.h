@@ -260,8 +260,26 @@ smdl_status smdl_prop_create(smdl_t h, int n_layers, const int* widths,
                              smdl_prop_t* p);
 smdl_status smdl_prop_destroy(smdl_prop_t p);
 
+/*
+ * smdl_prop_create with seeded Kaiming-uniform initial weights: W_l entries drawn from
+ * U(-sqrt(6/widths[l]), sqrt(6/widths[l])), b_l entries from U(-1/sqrt(widths[l]),
+ * 1/sqrt(widths[l])).  The uniforms are u = (z >> 11) * 2^-53 of consecutive splitmix64 outputs
+ * z (state = seed), used in the order W_0 (row-major), b_0, W_1, b_1, ...; each value is
+ * lo + (hi - lo) u computed in FP64 and rounded to FP32.  Same limits and errors as
+ * smdl_prop_create.
+ */
+smdl_status smdl_prop_create_seeded(smdl_t h, int n_layers, const int* widths, uint64_t seed,
+                                    smdl_prop_t* p);
+
 /* Copy the FP32 master weights and biases out to host arrays (one per layer). */
 smdl_status smdl_prop_get(smdl_t h, smdl_prop_t p, float* const* W_host, float* const* b_host);
+
+/*
+ * Replace the weights and biases (host arrays per layer, shapes as at creation, copied) and
+ * restart training: the Adam moments and step count are reset to zero and the BF16 copies
+ * rebuilt.  Synchronous.  SMDL_E_STATE if p belongs to another handle.
+ */
+smdl_status smdl_prop_set(smdl_t h, smdl_prop_t p, const float* const* W_host, const float* const* b_host);
 
 /* Logits (N x K, row n = signal n) of the network for signals Y (m x N). */
 smdl_status smdl_prop_logits(smdl_t h, smdl_prop_t p, const float* Y, int64_t N, float* logits);

@@ -83,6 +83,8 @@ def _load():
                              C.POINTER(C.POINTER(C.c_float)), C.POINTER(vp)],
         "smdl_prop_destroy": [vp],
         "smdl_prop_get": [vp, vp, C.POINTER(C.POINTER(C.c_float)), C.POINTER(C.POINTER(C.c_float))],
+        "smdl_prop_create_seeded": [vp, i32, C.POINTER(C.c_int), C.c_uint64, C.POINTER(vp)],
+        "smdl_prop_set": [vp, vp, C.POINTER(C.POINTER(C.c_float)), C.POINTER(C.POINTER(C.c_float))],
         "smdl_prop_logits": [vp, vp, vp, i64, vp],
         "smdl_prop_grad": [vp, vp, vp, i64, _Codes, C.POINTER(C.c_float), C.POINTER(vp), C.POINTER(vp)],
         "smdl_prop_train": [vp, vp, vp, i64, _Codes, C.POINTER(_TrainOpts), C.POINTER(C.c_float)],
@@ -351,6 +353,11 @@ class Handle:
     def proposer(self, Ws, bs) -> "Proposer":
         return Proposer(self, Ws, bs)
 
+    def proposer_seeded(self, widths, seed: int) -> "Proposer":
+        """A proposer with seeded Kaiming-uniform initial weights drawn on the host by the
+        library (splitmix64 uniforms)."""
+        return Proposer(self, None, None, widths=widths, seed=seed)
+
     def omp_code_proposed(self, prop: "Proposer", D: torch.Tensor, Y: torch.Tensor, s_max: int, n_cand: int,
                           eps_fallback: float, want_cand: bool = False):
         K, m = D.shape
@@ -374,17 +381,40 @@ class Handle:
 class Proposer:
     """The learned support proposer: an MLP y/||y|| -> one logit per atom (on the GPU)."""
 
-    def __init__(self, h: Handle, Ws, bs):
+    def __init__(self, h: Handle, Ws, bs, widths=None, seed=None):
         self.h = h
+        self._p = C.c_void_p(0)
+        if Ws is None:
+            self.widths = [int(w) for w in widths]
+            n = len(self.widths) - 1
+            wa = (C.c_int * (n + 1))(*self.widths)
+            h._check(lib().smdl_prop_create_seeded(h._h, n, wa, C.c_uint64(int(seed) & (2**64 - 1)),
+                                                   C.byref(self._p)))
+            return
         self.widths = [int(Ws[0].shape[1])] + [int(W.shape[0]) for W in Ws]
-        self._Ws = [np.ascontiguousarray(W, dtype=np.float32) for W in Ws]
-        self._bs = [np.ascontiguousarray(b, dtype=np.float32) for b in bs]
         n = len(Ws)
         wa = (C.c_int * (n + 1))(*self.widths)
-        WP = (C.POINTER(C.c_float) * n)(*[W.ctypes.data_as(C.POINTER(C.c_float)) for W in self._Ws])
-        BP = (C.POINTER(C.c_float) * n)(*[b.ctypes.data_as(C.POINTER(C.c_float)) for b in self._bs])
-        self._p = C.c_void_p(0)
+        WP, BP, keep = self._host_ptrs(Ws, bs)
         h._check(lib().smdl_prop_create(h._h, n, wa, WP, BP, C.byref(self._p)))
+
+    def _host_ptrs(self, Ws, bs):
+        n = self.n_layers
+        if len(Ws) != n or len(bs) != n:
+            raise ValueError(f"expected {n} weight matrices and bias vectors")
+        Ws = [np.ascontiguousarray(W, dtype=np.float32) for W in Ws]
+        bs = [np.ascontiguousarray(b, dtype=np.float32) for b in bs]
+        for l, (W, b) in enumerate(zip(Ws, bs)):
+            if W.shape != (self.widths[l + 1], self.widths[l]) or b.shape != (self.widths[l + 1],):
+                raise ValueError(f"layer {l}: W must be {(self.widths[l + 1], self.widths[l])}, "
+                                 f"b {(self.widths[l + 1],)}")
+        WP = (C.POINTER(C.c_float) * n)(*[W.ctypes.data_as(C.POINTER(C.c_float)) for W in Ws])
+        BP = (C.POINTER(C.c_float) * n)(*[b.ctypes.data_as(C.POINTER(C.c_float)) for b in bs])
+        return WP, BP, (Ws, bs)
+
+    def set_weights(self, Ws, bs):
+        """New weights and biases; the Adam state restarts from zero."""
+        WP, BP, keep = self._host_ptrs(Ws, bs)
+        self.h._check(lib().smdl_prop_set(self.h._h, self._p, WP, BP))
 
     def close(self):
         if self._p:

@@ -87,7 +87,7 @@ extern "C" smdl_status smdl_omp_code_noalloc(smdl_t h, const float* D, int m, in
     std::memset(&v, 0, sizeof(v));
     v.pd = PackDesc{D, frag, fhi, flo, aexp, K, Kpad};
     v.gd = GramDesc{frag, gram, Kpad, gld};
-    v.od = OmpDesc{frag, fhi, flo, aexp, gram, Y, N, 0, K, Kpad, s_max, gld};
+    v.od = OmpDesc{D, fhi, flo, aexp, gram, Y, N, 0, K, Kpad, s_max, gld};
     hipError_t e;
     hipLaunchKernelGGL(store_descs_kernel, dim3(1), dim3(64), 0, h->stream, v, dd);
     if ((e = hipGetLastError()) != hipSuccess) return h->hip(e, "descriptors");

@@ -29,6 +29,11 @@
 
 namespace smdl_omp {
 
+// The error-constrained stopping test recomputes the residual from the signal and the atoms when
+// the downdated ||r||^2 lies within this fraction of ||y||^2 of eps^2 (the downdated value carries
+// rounding errors of a few 2^-22 ||y||^2 per step).
+constexpr float EXPLICIT_MARGIN = 0x1p-13f;
+
 __device__ __forceinline__ float4 load_y4(const float* __restrict__ y, int r, int m, bool vec) {
     if (vec && r + 3 < m) return *reinterpret_cast<const float4*>(y + r);
     float4 v;
@@ -148,7 +153,56 @@ struct StepCtx {
     const float* arow;   // alpha0 of the signal (LDS), atom 0
     int g, s, gld, kpad;
     float eps2, tau, dep_tol, ynrm;
+    // explicit residuals: the dictionary (K atoms of m floats) and the signal, row r at
+    // yp[(r / 4) * ystr + r % 4] (the LDS copy, or memory with ystr = 4)
+    const float* D;
+    const float* yp;
+    int K, m, ystr;
+    float marg;          // |rn2 - eps2| below which the stopping test uses the explicit residual
 };
+
+// Value of lane I of the group of G lanes (I static): v_readlane for a whole-wave group,
+// otherwise ds_swizzle in bit mode (source lane = (lane & and_mask) | or_mask within 32 lanes).
+template <int G, int I>
+__device__ __forceinline__ int group_bcast(int v) {
+    if constexpr (G == 64) return __builtin_amdgcn_readlane(v, I);
+    else return __builtin_amdgcn_ds_swizzle(v, (I << 5) | (G == 16 ? 0x10 : 0x00));
+}
+
+// v - sum_{i in I...} x_i D[sel_i][r], x_i and sel_i taken from lane i of the group (only i < k).
+template <int G, int... I>
+__device__ __forceinline__ float sub_atoms(float v, float xg, int selg, int k, const float* D, int m, int r,
+                                           std::integer_sequence<int, I...>) {
+    ((v = fmaf(-__int_as_float(group_bcast<G, I>(__float_as_int(xg))),
+               D[(size_t)(I < k ? group_bcast<G, I>(selg) : 0) * m + r], v)),
+     ...);
+    return v;
+}
+
+// ||y - D_I x_I||^2 computed from the signal and the atoms (FP32), for the first k chosen atoms
+// (k <= KMAX) with x_I = Linv^T pi the least-squares coefficients on them.  Lane g takes rows
+// g, g + G, ...; every lane of the group gets the sum.  Indices of entries past k are replaced by
+// atom 0 with a zero coefficient, so every load stays inside D.
+template <int KMAX, int EM, int SM, int G>
+__device__ __forceinline__ float explicit_rn2(const State<EM, SM>& st, const StepCtx& x, int k) {
+    static_assert(KMAX <= SM, "at most SM atoms");
+    float xg = 0.f;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        const float t = fmaf(st.Lc[i], st.pi[i], xg);
+        xg = (i < k) ? t : xg;
+    }
+    xg = (x.g < k) ? xg : 0.f;
+    const int selg = ((uint32_t)st.sel < (uint32_t)x.K) ? st.sel : 0;
+    float acc = 0.f;
+#pragma unroll 1
+    for (int r = x.g; r < x.m; r += G) {
+        const float v = sub_atoms<G>(x.yp[(r >> 2) * x.ystr + (r & 3)], xg, selg, k, x.D, x.m, r,
+                                     std::make_integer_sequence<int, KMAX>{});
+        acc = fmaf(v, v, acc);
+    }
+    return group_sum<G>(acc);
+}
 
 // Global loads at a 32-bit byte offset from a wave-uniform base (global_load with a scalar
 // base address and a 32-bit vector offset).
@@ -164,7 +218,18 @@ __device__ __forceinline__ float gload(const float* base, uint32_t byte_off) {
 template <int KK, int EM, int SM, int G>
 __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
     if (KK >= x.s) return false;
-    if (x.eps2 > 0.f && !(st.rn2 > x.eps2)) st.live = false;
+    if (x.eps2 > 0.f) {
+        // error-constrained stop: ||r||^2 <= eps^2.  Near eps the downdated value (||y||^2 minus
+        // the squared projections) may have lost the digits that decide; there the residual is
+        // recomputed from the signal and the atoms.
+        bool stop = !(st.rn2 > x.eps2);
+        const bool near = st.live && fabsf(st.rn2 - x.eps2) <= x.marg;
+        if (__any(near)) {
+            const float e2 = explicit_rn2<KK, EM, SM, G>(st, x, KK);
+            stop = near ? !(e2 > x.eps2) : stop;
+        }
+        if (stop) st.live = false;
+    }
     if (!__any(st.live)) return false;
     const int g = x.g;
     // argmax |c| over the group: the exact maximum M, then the lowest atom index holding it.
@@ -543,6 +608,10 @@ __global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpAr
             ctx.eps2 = a.eps2;
             ctx.tau = a.tau;
             ctx.dep_tol = a.dep_tol;
+            ctx.D = d.D;
+            ctx.K = d.K;
+            ctx.m = a.m;
+            ctx.ystr = y_lds ? 4 * T : 4;
 #pragma unroll 1
             for (int p = 0; p < PASSES; ++p) {
                 const int sl = p * SPP + wave * GPW + grp;
@@ -561,14 +630,18 @@ __global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpAr
                 }
                 const float y2 = valid ? yn2[sl] : 0.f;
                 ctx.ynrm = sqrtf(y2);
+                ctx.marg = EXPLICIT_MARGIN * y2;
+                int64_t sig = it.first + (valid ? sl : 0);
+                if (a.sig_list) sig = a.sig_list[sig];
+                ctx.yp = y_lds ? ybuf + 4 * (valid ? sl : 0) : d.Y + sig * (int64_t)a.m;
                 st.rn2 = y2;
                 st.live = valid;
                 st.k = 0;
                 run_steps<EM, SM, G>(st, ctx, std::make_integer_sequence<int, SM>{});
+                // the residual norm from the signal and the atoms (not the downdated value)
+                const float rn2 = a.res ? explicit_rn2<SM, EM, SM, G>(st, ctx, st.k) : 0.f;
                 if (valid) {
-                    int64_t sig = it.first + sl;
-                    if (a.sig_list) sig = a.sig_list[sig];
-                    else sig += d.out0;
+                    if (!a.sig_list) sig += d.out0;
                     if (g < a.s_out) {
                         // x_I = Linv^T pi; lane g forms and writes entry g
                         int oi = -1;
@@ -586,7 +659,7 @@ __global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpAr
                     }
                     if (g == 0) {
                         a.nnz[sig] = st.k;
-                        if (a.res) a.res[sig] = sqrtf(fmaxf(st.rn2, 0.f));
+                        if (a.res) a.res[sig] = sqrtf(rn2);
                     }
                 }
                 __builtin_amdgcn_wave_barrier();

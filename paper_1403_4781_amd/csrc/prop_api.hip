@@ -262,6 +262,26 @@ smdl_status check_prop(smdl_t h, smdl_prop_t p) {
     return SMDL_OK;
 }
 
+// New FP32 masters (host arrays) with fresh Adam state (moments and step count zero) and
+// their BF16 copies; synchronous.
+smdl_status load_weights(smdl_t h, smdl_prop_t p, const float* const* W_host, const float* const* b_host) {
+    hipError_t e = hipMemsetAsync(p->dstep, 0, 4, h->stream);
+    for (int l = 0; l < p->n_layers && e == hipSuccess; ++l) {
+        const size_t nw = (size_t)p->widths[l] * p->widths[l + 1], nb = p->widths[l + 1];
+        e = hipMemcpyAsync(p->W[l], W_host[l], nw * 4, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(p->b[l], b_host[l], nb * 4, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(p->mW[l], 0, nw * 4, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(p->vW[l], 0, nw * 4, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(p->mb[l], 0, nb * 4, h->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(p->vb[l], 0, nb * 4, h->stream);
+        if (e == hipSuccess)
+            e = launch_to_bf16(p->W[l], (int64_t)nw, p->widths[l], p->widths[l + 1], p->Wpk[l], p->WTpk[l], h->stream);
+    }
+    if (e != hipSuccess) return h->hip(e, "proposer weights");
+    p->step = 0;
+    return h->hip(hipStreamSynchronize(h->stream), "proposer weights");
+}
+
 }  // namespace
 
 extern "C" smdl_status smdl_prop_create(smdl_t h, int n_layers, const int* widths, const float* const* W_init,
@@ -305,25 +325,58 @@ extern "C" smdl_status smdl_prop_create(smdl_t h, int n_layers, const int* width
         p->vb.push_back(vb);
         p->Wpk.push_back(Wpk);
         p->WTpk.push_back(WTpk);
-        hipError_t e = hipMemcpyAsync(W, W_init[l], nw * 4, hipMemcpyHostToDevice, h->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(b, b_init[l], nb * 4, hipMemcpyHostToDevice, h->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(mW, 0, nw * 4, h->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(vW, 0, nw * 4, h->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(mb, 0, nb * 4, h->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(vb, 0, nb * 4, h->stream);
-        if (e == hipSuccess) e = launch_to_bf16(W, (int64_t)nw, widths[l], widths[l + 1], Wpk, WTpk, h->stream);
-        if (e != hipSuccess) {
-            smdl_prop_destroy(p);
-            return h->hip(e, "proposer init");
-        }
     }
-    smdl_status st = h->hip(hipStreamSynchronize(h->stream), "proposer init");
+    smdl_status st = load_weights(h, p, W_init, b_init);
     if (st != SMDL_OK) {
         smdl_prop_destroy(p);
         return st;
     }
     *out = p;
     return SMDL_OK;
+}
+
+extern "C" smdl_status smdl_prop_create_seeded(smdl_t h, int n_layers, const int* widths, uint64_t seed,
+                                               smdl_prop_t* out) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    if (!out || !widths) return h->fail(SMDL_E_ARG, "null pointer");
+    if (n_layers < 1 || n_layers > 4) return h->fail(SMDL_E_SHAPE, "1 to 4 layers");
+    for (int l = 0; l <= n_layers; ++l)
+        if (widths[l] < 32 || widths[l] > 4096 || widths[l] % 32)
+            return h->fail(SMDL_E_SHAPE, "layer widths must be multiples of 32 in [32, 4096]");
+    // Kaiming-uniform weights U(-sqrt(6/fan_in), sqrt(6/fan_in)) and biases
+    // U(-1/sqrt(fan_in), 1/sqrt(fan_in)); uniforms (x >> 11) 2^-53 of consecutive splitmix64
+    // draws, every layer's weights (row-major) then its biases, layer by layer
+    SplitMix64 g(seed);
+    auto uni = [&g](double lo, double hi) {
+        const double u = (double)(g.next() >> 11) * (1.0 / 9007199254740992.0);
+        return (float)(lo + (hi - lo) * u);
+    };
+    std::vector<std::vector<float>> Ws(n_layers), bs(n_layers);
+    std::vector<const float*> Wp(n_layers), bp(n_layers);
+    for (int l = 0; l < n_layers; ++l) {
+        const double fan_in = widths[l];
+        const double bw = std::sqrt(6.0 / fan_in), bb = 1.0 / std::sqrt(fan_in);
+        Ws[l].resize((size_t)widths[l] * widths[l + 1]);
+        bs[l].resize(widths[l + 1]);
+        for (float& w : Ws[l]) w = uni(-bw, bw);
+        for (float& b : bs[l]) b = uni(-bb, bb);
+        Wp[l] = Ws[l].data();
+        bp[l] = bs[l].data();
+    }
+    return smdl_prop_create(h, n_layers, widths, Wp.data(), bp.data(), out);
+}
+
+extern "C" smdl_status smdl_prop_set(smdl_t h, smdl_prop_t p, const float* const* W_host, const float* const* b_host) {
+    if (!h) return SMDL_E_ARG;
+    h->err.clear();
+    smdl_status st = check_prop(h, p);
+    if (st != SMDL_OK) return st;
+    if (!W_host || !b_host) return h->fail(SMDL_E_ARG, "null pointer");
+    for (int l = 0; l < p->n_layers; ++l)
+        if (!W_host[l] || !b_host[l]) return h->fail(SMDL_E_ARG, "null weights");
+    (void)hipSetDevice(h->device);
+    return load_weights(h, p, W_host, b_host);
 }
 
 extern "C" smdl_status smdl_prop_destroy(smdl_prop_t p) {

@@ -236,7 +236,7 @@ smdl_status prepare_sets(smdl_t h, int m, std::vector<SetSpec>& sets, const char
         ko += (size_t)s.Kpad;
         pd[i] = PackDesc{s.D, s.frag, fhi, flo, ae, s.K, s.Kpad};
         gd[i] = GramDesc{s.frag, s.gram, s.Kpad, s.gld};
-        od[i] = OmpDesc{s.frag, fhi, flo, ae, s.gram, s.Y, s.n, s.out0, s.K, s.Kpad, s.s, s.gld};
+        od[i] = OmpDesc{s.D, fhi, flo, ae, s.gram, s.Y, s.n, s.out0, s.K, s.Kpad, s.s, s.gld};
     }
     plan.pack_desc = h->ws((t + ".pd").c_str(), pd.size() * sizeof(PackDesc));
     plan.gram_desc = h->ws((t + ".gd").c_str(), gd.size() * sizeof(GramDesc));

@@ -45,7 +45,7 @@ inline int pad16(int x) { return (x + 15) / 16 * 16; }
 
 // One dictionary and the signals coded against it.
 struct OmpDesc {
-    const float4* dfrag;  // packed fragments (mpad x Kpad floats)
+    const float* D;       // the dictionary, K rows of m floats (explicit residuals)
     const void* fhi;      // FP16 split fragments, hi and lo halves (mpad x Kpad halves each)
     const void* flo;
     const int32_t* aexp;  // Kpad atom exponents of the split

@@ -299,3 +299,62 @@ def test_trained_network_gains(h, dev):
     assert res["trained"][1] > res["untrained"][1] + 0.25
     assert res["trained"][0] < res["untrained"][0]
     assert 0.99 <= res["trained"][2] <= 1.05
+
+
+def _kaiming_expected(widths, seed):
+    """The seeded initial weights as the header defines them, drawn with the oracle's own
+    splitmix64 (an independent implementation of the same published generator)."""
+    g = oracle.splitmix64(seed)
+
+    def draw(n, lo, hi):
+        u = np.array([(next(g) >> 11) for _ in range(n)], np.float64) * 2.0 ** -53
+        return (lo + (hi - lo) * u).astype(np.float32)
+
+    Ws, bs = [], []
+    for fi, fo in zip(widths[:-1], widths[1:]):
+        bw, bb = np.sqrt(6.0 / fi), 1.0 / np.sqrt(fi)
+        Ws.append(draw(fi * fo, -bw, bw).reshape(fo, fi))
+        bs.append(draw(fo, -bb, bb))
+    return Ws, bs
+
+
+def test_seeded_creation_and_weight_setter(h, dev):
+    widths = [64, 128, 256]
+    print("case seeded proposer", flush=True)
+    p = h.proposer_seeded(widths, 99)
+    Ws, bs = p.weights()
+    We, be = _kaiming_expected(widths, 99)
+    for l in range(2):
+        np.testing.assert_array_equal(Ws[l], We[l])
+        np.testing.assert_array_equal(bs[l], be[l])
+    q = h.proposer_seeded(widths, 100)
+    assert not np.array_equal(q.weights()[0][0], Ws[0])
+    q.close()
+    D, Y, _ = synth.small_problem(4010, 64, 256, 8, 0.02, 512)
+    lg = p.logits(_t(Y, dev)).cpu().numpy()
+    assert _relfro(lg, oracle.mlp_forward(Ws, bs, Y)) <= REL
+    print("case weight setter", flush=True)
+    W2, b2 = synth.mlp_init(widths, seed=14)
+    labels = _codes_t(oracle.omp(D, Y, 8), dev)
+    p.train(_t(Y, dev), labels, epochs=2, batch=256, lr=1e-3)     # moves weights and Adam state
+    p.set_weights(W2, b2)
+    got_W, got_b = p.weights()
+    for l in range(2):
+        np.testing.assert_array_equal(got_W[l], W2[l].astype(np.float32))
+        np.testing.assert_array_equal(got_b[l], b2[l].astype(np.float32))
+    lg2 = p.logits(_t(Y, dev)).cpu().numpy()
+    assert _relfro(lg2, oracle.mlp_forward(W2, b2, Y)) <= REL
+    # training restarts: one step after the reset matches one step of a fresh proposer
+    fresh = h.proposer(W2, b2)
+    for r in (p, fresh):
+        r.train(_t(Y, dev), labels, epochs=1, batch=512, lr=1e-3)
+    Wa, _ = fresh.weights()
+    Wb, _ = p.weights()
+    for l in range(2):
+        e = _relfro(Wb[l].astype(np.float64) - W2[l], Wa[l].astype(np.float64) - W2[l])
+        print(f"  layer {l} step after reset vs fresh rel {e:.2e}", flush=True)
+        assert e <= 1e-3
+    with pytest.raises(ValueError):
+        p.set_weights(W2[:1], b2[:1])
+    p.close()
+    fresh.close()
