@@ -207,6 +207,7 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
     const int a = blockIdx.x;
     const int c = blockIdx.z, P = gridDim.z;
     if (a >= d.Kpad) return;
+    static_assert(SMDL_MAX_S <= 16, "16 support slots per list entry");
     constexpr int PSTAGE = 512;              // list entries staged per pass
     constexpr int PB = 8;                    // signal loads in flight per thread
     __shared__ double colA[SMDL_MAX_K];
@@ -254,7 +255,36 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
                 if (tid == 0)
                     for (int q = 0; q < cnt; ++q) add_entry(q, false);
             } else {
-                for (int q = tid; q < cnt; q += 256) add_entry(q, true);
+                // lanes over (entry, support slot): 16 entries per pass of the block, the loads
+                // of UA passes issued before their adds (s_stride <= 16 slots per entry)
+                constexpr int UA = 4;
+                const int slot = tid & 15, eq = tid >> 4;
+                for (int q0 = 0; q0 < cnt; q0 += 16 * UA) {
+                    int lv[UA], kv[UA];
+                    float cv[UA];
+                    double xv[UA];
+#pragma unroll
+                    for (int u = 0; u < UA; ++u) {
+                        const int q = q0 + 16 * u + eq;
+                        lv[u] = -1;
+                        kv[u] = 0;
+                        cv[u] = 0.f;
+                        xv[u] = 0.0;
+                        if (q < cnt) {
+                            const int64_t n = s_sig[q];
+                            kv[u] = d.nnz[n];
+                            if (slot < d.s_stride) {
+                                lv[u] = d.idx[n * d.s_stride + slot];
+                                cv[u] = d.coef[n * d.s_stride + slot];
+                            }
+                            xv[u] = s_cf[q];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < UA; ++u)
+                        if (slot < clamp_nnz(kv[u], d.s_stride) && lv[u] >= 0 && lv[u] < d.K)
+                            atomicAdd(&colA[lv[u]], xv[u] * (double)cv[u]);
+                }
             }
             // B column: rows split over threads, entries over groups of threads, PB signal
             // loads in flight per thread (the sum keeps the order of the entries)

@@ -156,13 +156,43 @@ def test_learn_matches_oracle_statistically(h, dev):
     r_g = rmse(Dg.cpu().numpy(), Yp, *to_np(Xg))
     r_o = rmse(Dr, Yp, cr.idx, cr.coef, cr.nnz)
     print(f"  rmse gpu {r_g:.6e} oracle {r_o:.6e}", flush=True)
-    assert abs(r_g - r_o) <= 1e-3 * r_o
+    # the free-running trajectories part at the first correlation tie (on this workload a top-2
+    # gap of 4e-9 at iteration 1), after which both are valid runs of the method
+    assert abs(r_g - r_o) <= 5e-3 * r_o
     # iteration 0 is exact: the initial dictionary and its first coding
     D0g, X0g = h.learn(_t(Yp, dev), 128, 5, 0)
     D0r, c0r = oracle.learn(Yp, 128, 5, 0)
     assert np.abs(D0g.cpu().numpy() - D0r).max() <= 1e-6
     ora = oracle.omp(D0g.cpu().numpy(), Yp, 5, trace=True)
     compare(to_np(X0g), ora, D0g.cpu().numpy(), Yp, label="learn iter0")
+
+
+def test_learn_trajectory_teacher_forced(h, dev):
+    """Every step of the GPU's own 10-iteration trajectory against the oracle (bitwise
+    reproducible runs, so that the run of it + 1 iterations repeats the run of it): the coding of
+    iteration it with the GPU's D_it at the OMP parity bar, and D_{it+1} against the oracle's MOD
+    of the GPU's codes at the MOD bar."""
+    import paper_1403_4781_amd as smdl
+    w = synth.oracle_scale()
+    Yp = w.Y[w.perm]
+    Yt = _t(Yp, dev)
+    h.set_flags(smdl.SMDL_DETERMINISTIC)
+    h.set_autotune(False)                 # one tile for every run
+    try:
+        Dg, Xg = h.learn(Yt, 128, 5, 0)
+        for it in range(10):
+            print(f"case learn trajectory iteration {it}", flush=True)
+            D = Dg.cpu().numpy()
+            gi, gc, gn = to_np(Xg)
+            compare((gi, gc, gn), oracle.omp(D, Yp, 5, trace=True), D, Yp, label=f"trajectory coding {it}")
+            Dref, nu_ref, _ = oracle.mod_update(Yp, oracle.Codes(gi, gc, gn), D)
+            Dg, Xg = h.learn(Yt, 128, 5, it + 1)
+            err = np.linalg.norm(Dg.cpu().numpy() - Dref, axis=1).max()
+            print(f"  D_{it + 1} max atom error {err:.3e}", flush=True)
+            assert err <= D_TOL
+    finally:
+        h.set_flags(0)
+        h.set_autotune(True)
 
 
 def test_one_iteration_teacher_forced(h, dev):
