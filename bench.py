@@ -50,13 +50,17 @@ def omp_alu_ops_per_signal(K: int, s: int) -> int:
     return s * K
 
 
+FP16_MFMA_PEAK = 2500.0    # TFLOP/s, MI355X dense FP16 matrix cores
+
+
 def omp_mix_ceiling(m: int, K: int, s: int) -> float:
-    """The ceiling this build's flop mix faces: the correlations on the FP32 matrix cores at
-    157.3 TFLOP/s, the rest on the vector ALUs, which issue at most 78.6 TFLOP/s without packed
-    FP32 instructions (this build does not emit them): the harmonic combination."""
+    """The ceiling this build's flop mix faces: the correlations on the FP16 matrix cores, three
+    products per FP32 product (the hi/lo split) at 2.5 PFLOP/s, the rest on the vector ALUs, which
+    issue at most 78.6 TFLOP/s without packed FP32 instructions (this build does not emit them):
+    the harmonic combination, in algorithmic FP32 flops per second."""
     f = omp_flops_per_signal(m, K, s)
     a0 = 2 * m * K
-    return f / (a0 / FP32_PEAK + (f - a0) / FP32_VALU_UNPACKED)
+    return f / (3 * a0 / FP16_MFMA_PEAK + (f - a0) / FP32_VALU_UNPACKED)
 
 
 def omp_bytes_per_signal(m: int, s: int) -> int:
@@ -577,7 +581,7 @@ def main():
         torch.cuda.synchronize()
         info["train_ms"] = (time.perf_counter() - t0) * 1e3
         t0 = time.perf_counter()
-        Xp, rn = h.omp_code(D, Ye, 8, res_norm=True)
+        Xp = h.omp_code(D, Ye, 8)
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         info["plain_kernel_ms"] = h.last_kernel_ms()
@@ -679,9 +683,10 @@ def main():
                      "kernel_ms": kms,
                      "mix_ceiling": {"peak": omp_mix_ceiling(64, 256, 8), "frac": achieved / omp_mix_ceiling(64, 256, 8),
                                      "unit": "TFLOP/s",
-                                     "derivation": "correlations (2mK flops) at the 157.3 TFLOP/s FP32 matrix-core "
-                                                   "peak, the other flops at 78.6 TFLOP/s (FP32 vector issue "
-                                                   "without packed FP32), combined harmonically"}},
+                                     "derivation": "correlations (2mK flops) as three FP16 products each at the "
+                                                   "2.5 PFLOP/s FP16 matrix-core peak, the other flops at 78.6 "
+                                                   "TFLOP/s (FP32 vector issue without packed FP32), combined "
+                                                   "harmonically"}},
     }
     eq = [c for c in curve if c["rmse_ratio"] <= 1.01]
     if eq:

@@ -179,10 +179,54 @@ __device__ __forceinline__ float sub_atoms(float v, float xg, int selg, int k, c
     return v;
 }
 
+// x_i and the address of atom sel_i, taken from lane i of the group, for every i in I... (atom 0
+// and a zero coefficient for i >= k).
+template <int G, int... I>
+__device__ __forceinline__ void bcast_atoms(float xg, int selg, int k, const float* D, int m, float* xb,
+                                            const float** db, std::integer_sequence<int, I...>) {
+    ((xb[I] = __int_as_float(group_bcast<G, I>(__float_as_int(xg))),
+      db[I] = D + (size_t)(I < k ? group_bcast<G, I>(selg) : 0) * m),
+     ...);
+}
+
 // ||y - D_I x_I||^2 computed from the signal and the atoms (FP32), for the first k chosen atoms
 // (k <= KMAX) with x_I = Linv^T pi the least-squares coefficients on them.  Lane g takes rows
 // g, g + G, ...; every lane of the group gets the sum.  Indices of entries past k are replaced by
 // atom 0 with a zero coefficient, so every load stays inside D.
+// The same in row groups of four (m % 4 == 0, D and the signal rows 16-byte aligned): lane g takes
+// row groups g, g + G, ...; the coefficients and atom indices are broadcast once; one 16-byte load
+// per atom and row group.
+template <int KMAX, int EM, int SM, int G>
+__device__ __forceinline__ float explicit_rn2_v4(const State<EM, SM>& st, const StepCtx& x, int k) {
+    static_assert(KMAX <= SM, "at most SM atoms");
+    float xg = 0.f;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        const float t = fmaf(st.Lc[i], st.pi[i], xg);
+        xg = (i < k) ? t : xg;
+    }
+    xg = (x.g < k) ? xg : 0.f;
+    const int selg = ((uint32_t)st.sel < (uint32_t)x.K) ? st.sel : 0;
+    float xb[KMAX];
+    const float* db[KMAX];
+    bcast_atoms<G>(xg, selg, k, x.D, x.m, xb, db, std::make_integer_sequence<int, KMAX>{});
+    float acc = 0.f;
+#pragma unroll 1
+    for (int q = x.g; 4 * q < x.m; q += G) {
+        float4 v = *reinterpret_cast<const float4*>(x.yp + q * x.ystr);
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+            const float4 d = *reinterpret_cast<const float4*>(db[i] + 4 * q);
+            v.x = fmaf(-xb[i], d.x, v.x);
+            v.y = fmaf(-xb[i], d.y, v.y);
+            v.z = fmaf(-xb[i], d.z, v.z);
+            v.w = fmaf(-xb[i], d.w, v.w);
+        }
+        acc = fmaf(v.x, v.x, fmaf(v.y, v.y, fmaf(v.z, v.z, fmaf(v.w, v.w, acc))));
+    }
+    return group_sum<G>(acc);
+}
+
 template <int KMAX, int EM, int SM, int G>
 __device__ __forceinline__ float explicit_rn2(const State<EM, SM>& st, const StepCtx& x, int k) {
     static_assert(KMAX <= SM, "at most SM atoms");
@@ -612,6 +656,9 @@ __global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpAr
             ctx.K = d.K;
             ctx.m = a.m;
             ctx.ystr = y_lds ? 4 * T : 4;
+            // row groups of four for the final residual when every row group is 16-byte aligned
+            const bool res_v4 = (a.m & 3) == 0 && (reinterpret_cast<uintptr_t>(d.D) & 15) == 0 &&
+                                (y_lds || (reinterpret_cast<uintptr_t>(d.Y) & 15) == 0);
 #pragma unroll 1
             for (int p = 0; p < PASSES; ++p) {
                 const int sl = p * SPP + wave * GPW + grp;
@@ -639,7 +686,11 @@ __global__ __launch_bounds__(256, (EM * SM >= 256) ? 1 : 2) void omp_fused(OmpAr
                 st.k = 0;
                 run_steps<EM, SM, G>(st, ctx, std::make_integer_sequence<int, SM>{});
                 // the residual norm from the signal and the atoms (not the downdated value)
-                const float rn2 = a.res ? explicit_rn2<SM, EM, SM, G>(st, ctx, st.k) : 0.f;
+                float rn2 = 0.f;
+                if (a.res) {
+                    if (res_v4) rn2 = explicit_rn2_v4<SM, EM, SM, G>(st, ctx, st.k);
+                    else rn2 = explicit_rn2<SM, EM, SM, G>(st, ctx, st.k);
+                }
                 if (valid) {
                     if (!a.sig_list) sig += d.out0;
                     if (g < a.s_out) {

@@ -358,3 +358,21 @@ def test_seeded_creation_and_weight_setter(h, dev):
         p.set_weights(W2[:1], b2[:1])
     p.close()
     fresh.close()
+
+
+@pytest.mark.parametrize("widths", [[64, 512, 256], [64, 128, 256]])
+def test_candidates_are_the_top_logits(h, dev, widths):
+    """The candidate sets are exactly the n_c largest of the network's own logits (lower atom
+    first on equal logits), for two networks, 1000 rows (a ragged last work group)."""
+    Ws, bs = synth.mlp_init(widths, seed=15)
+    D, Y, _ = synth.small_problem(4011, 64, 256, 8, 0.02, 1000)
+    print(f"case candidates {widths}", flush=True)
+    p = h.proposer(Ws, bs)
+    Yt = _t(Y, dev)
+    lg = p.logits(Yt).cpu().numpy()
+    _, _, _, cand = h.omp_code_proposed(p, _t(D, dev), Yt, 8, 24, float("inf"), want_cand=True)
+    idx = np.broadcast_to(np.arange(256), lg.shape)
+    order = np.lexsort((idx, -lg.astype(np.float64)), axis=1)
+    ref = np.sort(order[:, :24], axis=1)
+    np.testing.assert_array_equal(cand.cpu().numpy(), ref)
+    p.close()
