@@ -131,6 +131,12 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
+// Whether a tile keeps the directions scaled (u_i) rather than unscaled (v_i = l_i u_i, with the
+// 1 / l_i applied to the k coefficients of each update instead): scaled costs EM multiplies per
+// step and saves the SM registers of the 1 / l_i, which the 16-step tiles need.
+template <int SM>
+constexpr bool SCALED_U = SM >= 12;
+
 // Per-signal state of the greedy loop, in registers.  The inverse Cholesky factor Linv of G_II
 // is held by columns: lane g of the group keeps column g (Linv[i][g], zero for i < g), and the
 // lane g < k keeps the atom chosen at step g.  Entries of step i are written only when the
@@ -138,10 +144,10 @@ __device__ __forceinline__ float group_sum(float v) {
 template <int EM, int SM>
 struct State {
     float c[EM];         // correlations of the residual with this lane's atoms
-    float U[SM][EM];     // unscaled directions v_i = l_i u_i at this lane's atoms
+    float U[SM][EM];     // directions at this lane's atoms: v_i = l_i u_i, or u_i (SCALED_U)
     float Lc[SM];        // Linv[i][g]
     float pi[SM];        // pi_i = c_j / l_i of step i
-    float rl[SM];        // 1 / l_i
+    float rl[SM];        // 1 / l_i (unscaled directions only)
     int sel;             // atom chosen at step g
     float rn2;           // ||r||^2
     int k;               // atoms chosen
@@ -289,18 +295,22 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
     // (j is a valid atom whenever M is a finite maximum; the test keeps any other case away
     // from the loads below)
     if (!(M > x.tau * x.ynrm) || (uint32_t)j >= (uint32_t)x.kpad) st.live = false;
+    // the last step of the tile updates neither U nor the correlations: nothing reads them after it
+    constexpr bool UPDATE = KK + 1 < SM;
     if (st.live) {
         // 32-bit offsets from the (uniform) Gram base: global loads with a scalar base
         const uint32_t row = (uint32_t)j * (uint32_t)x.gld * 4u;   // bytes
         // row j of G at this lane's atoms (columns < EM * G <= gld: no guard needed)
         float gr[EM];
+        if (UPDATE) {
 #pragma unroll
-        for (int q = 0; q < EM / 4; ++q) {
-            const f32x4 v = gload4(x.gram, row + (uint32_t)(16 * G * q + 16 * g));
-            gr[4 * q + 0] = v[0];
-            gr[4 * q + 1] = v[1];
-            gr[4 * q + 2] = v[2];
-            gr[4 * q + 3] = v[3];
+            for (int q = 0; q < EM / 4; ++q) {
+                const f32x4 v = gload4(x.gram, row + (uint32_t)(16 * G * q + 16 * g));
+                gr[4 * q + 0] = v[0];
+                gr[4 * q + 1] = v[1];
+                gr[4 * q + 2] = v[2];
+                gr[4 * q + 3] = v[3];
+            }
         }
         // lane g < k: G[j, sel_g]
         const bool mine = g < KK;
@@ -330,17 +340,20 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
             const float pk = cj * rl;
             // U keeps the unscaled direction v_k = G[:, j] - sum_i u_i w_i, u_k = v_k / l_k: the
             // scale moves onto the k coefficients (w_i / l_i) and onto pi_k / l_k
-            float wv[KK > 0 ? KK : 1];
+            if (UPDATE) {
+                // (SCALED_U: U holds u_k = v_k / l_k itself, so that the 1 / l_i need no registers)
+                float wv[KK > 0 ? KK : 1];
 #pragma unroll
-            for (int i = 0; i < KK; ++i) wv[i] = w[i] * st.rl[i];
-            const float pkr = ok ? pk * rl : 0.f;
+                for (int i = 0; i < KK; ++i) wv[i] = SCALED_U<SM> ? w[i] : w[i] * st.rl[i];
+                const float pkr = ok ? pk * rl : 0.f;
 #pragma unroll
-            for (int t = 0; t < EM; ++t) {
-                float v = gr[t];
+                for (int t = 0; t < EM; ++t) {
+                    float v = gr[t];
 #pragma unroll
-                for (int i = 0; i < KK; ++i) v = fmaf(-st.U[i][t], wv[i], v);
-                st.U[KK][t] = v;
-                st.c[t] = fmaf(-pkr, v, st.c[t]);
+                    for (int i = 0; i < KK; ++i) v = fmaf(-st.U[i][t], wv[i], v);
+                    st.U[KK][t] = SCALED_U<SM> ? v * rl : v;
+                    st.c[t] = fmaf(-pkr, v, st.c[t]);
+                }
             }
             // Linv row k = (-(w^T Linv) / l, 1 / l): lane g forms entry g
             float hg = 0.f;
@@ -348,7 +361,7 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
             for (int i = 0; i < KK; ++i) hg = fmaf(w[i], st.Lc[i], hg);
             st.Lc[KK] = mine ? -hg * rl : (g == KK ? rl : 0.f);
             st.pi[KK] = pk;
-            st.rl[KK] = rl;
+            if (!SCALED_U<SM>) st.rl[KK] = rl;
             st.sel = (g == KK) ? j : st.sel;
             st.rn2 = ok ? fmaf(-pk, pk, st.rn2) : st.rn2;
             st.k = ok ? KK + 1 : st.k;
