@@ -34,19 +34,22 @@ __global__ void pack_dict_kernel(const PackDesc* __restrict__ pd, int m, int mch
 }
 
 // Exponent of every atom for the FP16 split: max_r |D[r][k]| * 2^-aexp[k] in [0.5, 1) (0 for a
-// zero atom and for the padding atoms).  One thread per atom, grid.y = dictionary.
-__global__ void atom_exp_kernel(const PackDesc* __restrict__ pd, int m) {
+// zero atom and for the padding atoms).  One wave per atom (coalesced rows, a shuffle maximum),
+// four atoms per block, grid.y = dictionary.
+__global__ __launch_bounds__(256) void atom_exp_kernel(const PackDesc* __restrict__ pd, int m) {
     const PackDesc p = pd[blockIdx.y];
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (k >= p.Kpad) return;
     float mx = 0.f;
     if (k < p.K) {
         const float* col = p.D + (int64_t)k * m;
-        for (int r = 0; r < m; ++r) mx = fmaxf(mx, fabsf(col[r]));
+        for (int r = lane; r < m; r += 64) mx = fmaxf(mx, fabsf(col[r]));
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
     int e = 0;
     if (mx > 0.f) (void)frexpf(mx, &e);
-    p.aexp[k] = e;
+    if (lane == 0) p.aexp[k] = e;
 }
 
 // The FP16 split fragments (layout at OmpDesc).  One thread per lane quadruple.
@@ -308,7 +311,7 @@ hipError_t launch_pack_dict_m(const void* dev_pack_desc, int n_dict, int max_kpa
                        static_cast<const PackDesc*>(dev_pack_desc), m, mchunks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(atom_exp_kernel, dim3((max_kpad + 255) / 256, n_dict), dim3(256), 0, st,
+    hipLaunchKernelGGL(atom_exp_kernel, dim3((max_kpad + 3) / 4, n_dict), dim3(256), 0, st,
                        static_cast<const PackDesc*>(dev_pack_desc), m);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // the split covers every 64-row chunk (mpad rows): the 16-row blocks past m are zero
