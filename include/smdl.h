@@ -164,6 +164,10 @@ typedef struct {
                                        thread), so that repeated runs give the same bits      */
 #define SMDL_CHECK_FINITE 16u       /* reject non-finite signals with SMDL_E_NUMERIC before any
                                        other work                                            */
+#define SMDL_ASYNC 32u              /* handle option (smdl_set_flags): smdl_omp_code,
+                                       smdl_omp_code_noalloc, smdl_gram and smdl_prop_logits
+                                       return once their work is queued on the handle's stream
+                                       (see smdl_set_flags)                                  */
 
 typedef struct {
     int iters_local;   /* alternations on every subset (step 2)                               */
@@ -351,10 +355,16 @@ smdl_status smdl_set_tile(smdl_t h, int K, int s_max, int lanes_per_signal, int 
 smdl_status smdl_set_mod_solver(smdl_t h, int mode);
 /*
  * Options of every later call on the handle: SMDL_DETERMINISTIC (MOD products in a fixed order,
- * for smdl_mod_update, smdl_learn* and smdl_split_merge_learn) and SMDL_CHECK_FINITE (the input
+ * for smdl_mod_update, smdl_learn* and smdl_split_merge_learn), SMDL_CHECK_FINITE (the input
  * signals, and for smdl_omp_code the dictionary, are checked first; a NaN or infinity returns
- * SMDL_E_NUMERIC and nothing else runs).  0 clears both.  SMDL_E_ARG for any other bit.
- * smdl_split_merge_learn uses these bits OR-ed with smdl_learn_opts.flags.
+ * SMDL_E_NUMERIC and nothing else runs) and SMDL_ASYNC.  0 clears them.  SMDL_E_ARG for any
+ * other bit.  smdl_split_merge_learn uses these bits OR-ed with smdl_learn_opts.flags.
+ * SMDL_ASYNC: smdl_omp_code, smdl_omp_code_noalloc, smdl_gram and smdl_prop_logits return as soon
+ * as their work is queued on the handle's stream (the other calls stay synchronous).  Their device
+ * outputs are valid once the caller has synchronised that stream; the inputs must stay unchanged
+ * until then; an error inside the queued kernels is reported by the next call that synchronises.
+ * An autotuning first call of a shape, and a SMDL_CHECK_FINITE check, still synchronise.
+ * smdl_last_kernel_ms waits for the timed launch.
  */
 smdl_status smdl_set_flags(smdl_t h, uint32_t flags);
 /* Enable (default) or disable automatic tuning on the first learning call of a shape. */

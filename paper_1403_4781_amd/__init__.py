@@ -28,6 +28,7 @@ SMDL_NO_GRAPH = 2
 SMDL_COMPOSE_CODES = 4
 SMDL_DETERMINISTIC = 8
 SMDL_CHECK_FINITE = 16
+SMDL_ASYNC = 32
 
 _STATUS = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_UNSUPPORTED", -4: "E_NOMEM", -5: "E_HIP",
            -6: "E_NUMERIC", -7: "E_STATE"}
@@ -343,7 +344,9 @@ class Handle:
         self._check(lib().smdl_set_mod_solver(self._h, mode))
 
     def set_flags(self, flags: int):
-        """Handle-wide options: SMDL_DETERMINISTIC | SMDL_CHECK_FINITE (0 clears)."""
+        """Handle-wide options: SMDL_DETERMINISTIC | SMDL_CHECK_FINITE | SMDL_ASYNC (0 clears).
+        With SMDL_ASYNC the coding, Gram and logit calls return once queued on the handle's stream:
+        synchronise (torch.cuda.synchronize()) before reading their outputs."""
         self._check(lib().smdl_set_flags(self._h, int(flags)))
 
     def set_autotune(self, enabled: bool):

@@ -114,6 +114,6 @@ extern "C" smdl_status smdl_omp_code_noalloc(smdl_t h, const float* D, int m, in
     // under graph capture the work is only recorded; otherwise the call returns when it is done
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if ((e = hipStreamIsCapturing(h->stream, &cap)) != hipSuccess) return h->hip(e, "capture status");
-    if (cap != hipStreamCaptureStatusNone) return SMDL_OK;
+    if (cap != hipStreamCaptureStatusNone || (h->flags & SMDL_ASYNC)) return SMDL_OK;
     return h->hip(hipStreamSynchronize(h->stream), "omp");
 }

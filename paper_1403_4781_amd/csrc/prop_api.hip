@@ -416,6 +416,7 @@ extern "C" smdl_status smdl_prop_logits(smdl_t h, smdl_prop_t p, const float* Y,
     Acts a;
     if ((st = get_acts(h, p, pad64b(N), false, a)) != SMDL_OK) return st;
     if ((st = h->hip(enqueue_logits(h, p, Y, N, a, logits), "forward")) != SMDL_OK) return st;
+    if (h->flags & SMDL_ASYNC) return SMDL_OK;
     return h->hip(hipStreamSynchronize(h->stream), "forward");
 }
 

@@ -21,7 +21,11 @@ void* smdl_ctx::ws(const char* name, size_t bytes) {
     Buf& b = bufs[name];
     if (bytes == 0) bytes = 16;
     if (b.cap >= bytes) return b.p;
-    if (b.p) (void)hipFree(b.p);
+    // (queued work of an asynchronous call may still use the old buffer)
+    if (b.p) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(b.p);
+    }
     b.p = nullptr;
     b.cap = 0;
     if (hipMalloc(&b.p, bytes) != hipSuccess) {
@@ -105,6 +109,13 @@ extern "C" const char* smdl_last_error(smdl_t h) { return h ? h->err.c_str() : "
 
 extern "C" smdl_status smdl_last_kernel_ms(smdl_t h, float* ms) {
     if (!h || !ms) return SMDL_E_ARG;
+    if (h->timed_pending) {
+        // an asynchronous call: wait for its timed launch
+        (void)hipSetDevice(h->device);
+        smdl_status st = h->hip(hipEventSynchronize(h->ev1), "timing");
+        if (st != SMDL_OK) return st;
+        finish_timing(h);
+    }
     *ms = h->last_kernel_ms;
     return SMDL_OK;
 }
@@ -345,6 +356,7 @@ extern "C" smdl_status smdl_gram(smdl_t h, const float* D, int m, int K, float* 
     const int ld = sets[0].gld;
     if ((st = h->hip(hipMemcpy2DAsync(G, (size_t)K * 4, sets[0].gram, (size_t)ld * 4, (size_t)K * 4, K,
                                       hipMemcpyDeviceToDevice, h->stream), "copy")) != SMDL_OK) return st;
+    if (h->flags & SMDL_ASYNC) return SMDL_OK;
     return h->hip(hipStreamSynchronize(h->stream), "gram");
 }
 
@@ -430,6 +442,7 @@ extern "C" smdl_status smdl_omp_code(smdl_t h, const float* D, int m, int K, con
         return st;
     if ((st = omp_code_impl(h, D, m, K, Y, N, s_max, eps, X, res_norm, nullptr, nullptr, 0, "omp")) != SMDL_OK)
         return st;
+    if (h->flags & SMDL_ASYNC) return SMDL_OK;   // timing read later by smdl_last_kernel_ms
     st = h->hip(hipStreamSynchronize(h->stream), "omp");
     finish_timing(h);
     return st;
@@ -1028,8 +1041,8 @@ extern "C" smdl_status smdl_set_mod_solver(smdl_t h, int mode) {
 
 extern "C" smdl_status smdl_set_flags(smdl_t h, uint32_t flags) {
     if (!h) return SMDL_E_ARG;
-    if (flags & ~(SMDL_DETERMINISTIC | SMDL_CHECK_FINITE))
-        return h->fail(SMDL_E_ARG, "only SMDL_DETERMINISTIC and SMDL_CHECK_FINITE apply to a handle");
+    if (flags & ~(SMDL_DETERMINISTIC | SMDL_CHECK_FINITE | SMDL_ASYNC))
+        return h->fail(SMDL_E_ARG, "only SMDL_DETERMINISTIC, SMDL_CHECK_FINITE and SMDL_ASYNC apply to a handle");
     h->flags = flags;
     return SMDL_OK;
 }

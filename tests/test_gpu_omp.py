@@ -174,3 +174,29 @@ def test_full_size_patch_workload_sampled(h, dev):
     rr = np.linalg.norm(w.Y[rs].astype(np.float64) - np.einsum('ns,nsm->nm', gc[rs], D.astype(np.float64)[np.maximum(gi[rs], 0)]), axis=1)
     yn = np.linalg.norm(w.Y[rs].astype(np.float64), axis=1)
     assert (np.abs(r.cpu().numpy()[rs] - rr) <= 1e-5 * rr + 2e-6 * yn).all()
+
+
+def test_async_calls_match_synchronous(h, dev):
+    """SMDL_ASYNC: the coding and Gram calls return once queued; after a device synchronisation
+    their outputs equal those of the synchronous calls bit for bit (a second, larger shape in
+    between makes the workspace grow while the first call's work may still be queued)."""
+    import paper_1403_4781_amd as smdl
+    D1, Y1, _ = synth.small_problem(2101, 64, 256, 8, 0.02, 3000)
+    D2, Y2, _ = synth.small_problem(2102, 64, 512, 8, 0.02, 5000)
+    t = [(_t(D1, dev), _t(Y1, dev)), (_t(D2, dev), _t(Y2, dev))]
+    print("case async", flush=True)
+    ref = [to_np(h.omp_code(Dt, Yt, 8)) for Dt, Yt in t]
+    gref = h.gram(t[1][0]).cpu().numpy()
+    h.set_flags(smdl.SMDL_ASYNC)
+    try:
+        got = [h.omp_code(Dt, Yt, 8) for Dt, Yt in t]
+        G = h.gram(t[1][0])
+        ms = h.last_kernel_ms()
+        torch.cuda.synchronize()
+    finally:
+        h.set_flags(0)
+    assert ms > 0.0
+    for a, b in zip(got, ref):
+        for x, y in zip(to_np(a), b):
+            np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(G.cpu().numpy(), gref)
