@@ -483,80 +483,87 @@ __device__ __forceinline__ void alpha0_phase(const OmpArgs& a, const OmpDesc& d,
         ye[tt] = (mx == 0.f || (mx >= 0.125f && mx < 16384.f)) ? 0 : e;
         ysq[tt] = 0.f;
     }
-    // The products over all 16-row blocks, with ||y||^2.  The fragments of all row blocks of a
-    // 16-row block are requested together, those of the next block while the current one is
-    // multiplied (row blocks past this wave's share are clamped to its last one, not used).
-    f32x4 acc[RBW][TT];
+    // The products over all 16-row blocks, with ||y||^2, in passes over at most four of the wave's
+    // row blocks (wide waves, RBW > 4, take two or more passes, each reading the signal rows again:
+    // a second register set of fragments for all their row blocks would not fit beside the
+    // accumulators).  The fragments of a pass's row blocks of one 16-row block are requested
+    // together, those of the next 16-row block while the current one is multiplied (row blocks
+    // past this wave's share are clamped to its last one, not used).
+    constexpr int RBH = RBW < 4 ? RBW : 4;
+    constexpr int NH = (RBW + RBH - 1) / RBH;
+#pragma unroll 1
+    for (int h = 0; h < NH; ++h) {
+        const int rbase = rb0 + h * RBH;
+        const int rbh = min(RBH, rbw - h * RBH);     // row blocks of this pass
+        if (rbh <= 0) break;
+        f32x4 acc[RBH][TT];
 #pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
+        for (int rb = 0; rb < RBH; ++rb)
 #pragma unroll
-        for (int tt = 0; tt < TT; ++tt) acc[rb][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    h4 nh[RBW], nl[RBW];
-    auto request = [&](int kb) {
+            for (int tt = 0; tt < TT; ++tt) acc[rb][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        h4 nh[RBH], nl[RBH];
+        auto request = [&](int kb) {
 #pragma unroll
-        for (int rb = 0; rb < RBW; ++rb) {
-            const size_t o = ((size_t)kb * NRB + rb0 + min(rb, rbw - 1)) * 64 + lane;
-            nh[rb] = fhi[o];
-            nl[rb] = flo[o];
-        }
-    };
-    // (wide waves, RBW > 4, request each block's fragments just before its products: the second
-    // register set would not fit beside the accumulators)
-    constexpr bool AHEAD = RBW <= 4;
-    if (AHEAD) request(0);
-    for (int kb = 0; kb < KB; ++kb) {
-        const int r = 16 * kb + 4 * kq;
-        if (!AHEAD) request(kb);
-        h4 ah[RBW], al[RBW];
+            for (int rb = 0; rb < RBH; ++rb) {
+                const size_t o = ((size_t)kb * NRB + rbase + min(rb, rbh - 1)) * 64 + lane;
+                nh[rb] = fhi[o];
+                nl[rb] = flo[o];
+            }
+        };
+        request(0);
+        for (int kb = 0; kb < KB; ++kb) {
+            const int r = 16 * kb + 4 * kq;
+            h4 ah[RBH], al[RBH];
 #pragma unroll
-        for (int rb = 0; rb < RBW; ++rb) {
-            ah[rb] = nh[rb];
-            al[rb] = nl[rb];
-        }
-        if (AHEAD && kb + 1 < KB) request(kb + 1);
-        h4 bh[TT], bl[TT];
+            for (int rb = 0; rb < RBH; ++rb) {
+                ah[rb] = nh[rb];
+                al[rb] = nl[rb];
+            }
+            if (kb + 1 < KB) request(kb + 1);
+            h4 bh[TT], bl[TT];
 #pragma unroll
-        for (int tt = 0; tt < TT; ++tt) {
-            float4 v = yrow(tt, r);
-            ysq[tt] += v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
-            v.x = ldexpf(v.x, -ye[tt]);
-            v.y = ldexpf(v.y, -ye[tt]);
-            v.z = ldexpf(v.z, -ye[tt]);
-            v.w = ldexpf(v.w, -ye[tt]);
-            bh[tt][0] = (_Float16)v.x;
-            bh[tt][1] = (_Float16)v.y;
-            bh[tt][2] = (_Float16)v.z;
-            bh[tt][3] = (_Float16)v.w;
-            bl[tt][0] = (_Float16)(v.x - (float)bh[tt][0]);
-            bl[tt][1] = (_Float16)(v.y - (float)bh[tt][1]);
-            bl[tt][2] = (_Float16)(v.z - (float)bh[tt][2]);
-            bl[tt][3] = (_Float16)(v.w - (float)bh[tt][3]);
-        }
+            for (int tt = 0; tt < TT; ++tt) {
+                float4 v = yrow(tt, r);
+                if (h == 0) ysq[tt] += v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+                v.x = ldexpf(v.x, -ye[tt]);
+                v.y = ldexpf(v.y, -ye[tt]);
+                v.z = ldexpf(v.z, -ye[tt]);
+                v.w = ldexpf(v.w, -ye[tt]);
+                bh[tt][0] = (_Float16)v.x;
+                bh[tt][1] = (_Float16)v.y;
+                bh[tt][2] = (_Float16)v.z;
+                bh[tt][3] = (_Float16)v.w;
+                bl[tt][0] = (_Float16)(v.x - (float)bh[tt][0]);
+                bl[tt][1] = (_Float16)(v.y - (float)bh[tt][1]);
+                bl[tt][2] = (_Float16)(v.z - (float)bh[tt][2]);
+                bl[tt][3] = (_Float16)(v.w - (float)bh[tt][3]);
+            }
 #pragma unroll
-        for (int rb = 0; rb < RBW; ++rb) {
-            if (rb < rbw) {
+            for (int rb = 0; rb < RBH; ++rb) {
+                if (rb < rbh) {
 #pragma unroll
-                for (int tt = 0; tt < TT; ++tt) {
-                    acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(al[rb], bh[tt], acc[rb][tt], 0, 0, 0);
-                    acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[rb], bl[tt], acc[rb][tt], 0, 0, 0);
-                    acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[rb], bh[tt], acc[rb][tt], 0, 0, 0);
+                    for (int tt = 0; tt < TT; ++tt) {
+                        acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(al[rb], bh[tt], acc[rb][tt], 0, 0, 0);
+                        acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[rb], bl[tt], acc[rb][tt], 0, 0, 0);
+                        acc[rb][tt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[rb], bh[tt], acc[rb][tt], 0, 0, 0);
+                    }
                 }
             }
         }
-    }
-    // D[i][j] of the 16x16 tile sits in lane j + 16*(i/4), register i%4:
-    // row i = atom 16*rb + 4*kq + q, column j = signal i16.  Undo the scales.
+        // D[i][j] of the 16x16 tile sits in lane j + 16*(i/4), register i%4:
+        // row i = atom 16*rb + 4*kq + q, column j = signal i16.  Undo the scales.
 #pragma unroll
-    for (int rb = 0; rb < RBW; ++rb) {
-        if (rb < rbw) {
-            const int atom0 = 16 * (rb0 + rb) + 4 * kq;
-            const int4 ea = *reinterpret_cast<const int4*>(d.aexp + atom0);
+        for (int rb = 0; rb < RBH; ++rb) {
+            if (rb < rbh) {
+                const int atom0 = 16 * (rbase + rb) + 4 * kq;
+                const int4 ea = *reinterpret_cast<const int4*>(d.aexp + atom0);
 #pragma unroll
-            for (int tt = 0; tt < TT; ++tt) {
-                float* dst = alpha + (16 * tt + i16) * stride + atom0;
-                *reinterpret_cast<float4*>(dst) =
-                    make_float4(ldexpf(acc[rb][tt][0], ea.x + ye[tt]), ldexpf(acc[rb][tt][1], ea.y + ye[tt]),
-                                ldexpf(acc[rb][tt][2], ea.z + ye[tt]), ldexpf(acc[rb][tt][3], ea.w + ye[tt]));
+                for (int tt = 0; tt < TT; ++tt) {
+                    float* dst = alpha + (16 * tt + i16) * stride + atom0;
+                    *reinterpret_cast<float4*>(dst) =
+                        make_float4(ldexpf(acc[rb][tt][0], ea.x + ye[tt]), ldexpf(acc[rb][tt][1], ea.y + ye[tt]),
+                                    ldexpf(acc[rb][tt][2], ea.z + ye[tt]), ldexpf(acc[rb][tt][3], ea.w + ye[tt]));
+                }
             }
         }
     }
