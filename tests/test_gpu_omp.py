@@ -125,6 +125,45 @@ def test_degenerate_signals(h, dev):
     assert X.nnz.shape == (0,)
 
 
+def test_exact_ties_in_every_tile(h, dev):
+    """Exact ties between copies of one atom, placed so that for each group width some copies
+    share a lane (same or another row of entries) and others sit in different lanes, including
+    copies whose higher index lies in a lower lane: the lowest index must win in every tile.
+    Signals are 2-sparse (weights 3 and 1) in the copied atoms, coded with s = 2, so that no other
+    pair of atoms comes near a tie and the comparison with the oracle is strict."""
+    rng = np.random.default_rng(2031)
+    m, K, s, N = 64, 256, 2, 600
+    D = rng.standard_normal((K, m))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    # (lower, higher) index of each copied pair; entry t of lane g of a 16-lane group holds atom
+    # 64 (t / 4) + 4 g + t % 4 (128 (t / 4) + ... for 32 lanes, 256 (t / 4) + ... for 64)
+    pairs = [(0, 4), (9, 10), (16, 80), (24, 156), (44, 236), (50, 131), (60, 65), (100, 228)]
+    for a, b in pairs:
+        D[b] = D[a]
+    D = D.astype(np.float32)
+    src = rng.integers(0, len(pairs), size=(N, 2))
+    src[:, 1] = (src[:, 0] + 1 + rng.integers(0, len(pairs) - 1, size=N)) % len(pairs)
+    lo = np.array([a for a, _ in pairs])
+    sg = rng.choice([-1.0, 1.0], size=(N, 2))
+    w = np.stack([3.0 * sg[:, 0], rng.uniform(0.8, 1.2, N) * sg[:, 1]], axis=1)
+    Y = (w[:, :1] * D[lo[src[:, 0]]] + w[:, 1:] * D[lo[src[:, 1]]]).astype(np.float32)
+    ora = oracle.omp(D, Y, s, trace=True)
+    assert set(np.unique(ora.idx)) <= set(lo.tolist())
+    Dt, Yt = _t(D, dev), _t(Y, dev)
+    tried = 0
+    for lanes in (16, 32, 64):
+        for spi in (16, 32, 64):
+            try:
+                h.set_tile(K, s, lanes, spi)
+            except Exception:
+                continue
+            print(f"case ties lanes={lanes} spi={spi}", flush=True)
+            X = h.omp_code(Dt, Yt, s)
+            compare(to_np(X), ora, D, Y, label=f"ties lanes{lanes} spi{spi}", ties=np.zeros(N, bool))
+            tried += 1
+    assert tried >= 3
+
+
 def test_output_stride_larger_than_sparsity(h, dev):
     import paper_1403_4781_amd as smdl
     D, Y, _ = synth.small_problem(2003, 64, 128, 4, 0.01, 100)
