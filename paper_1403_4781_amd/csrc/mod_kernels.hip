@@ -155,41 +155,92 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ 
     if (threadIdx.x == 1023) ptr[total] = part[1023];
 }
 
-// Each block reserves one contiguous range per atom in that atom's list (one global atomic per
-// atom with entries in the block), then places its entries through LDS cursors.
-__global__ __launch_bounds__(256) void csc_fill_kernel(const ModDesc* __restrict__ md, const int32_t* __restrict__ ptr,
-                                                       int32_t* __restrict__ fill, int32_t* __restrict__ list_sig,
-                                                       float* __restrict__ list_coef) {
+// Each block takes CSC_FILL_SIG signals, one per thread.  One LDS atomic per entry counts the
+// entries of each atom and gives the entry its rank among them; a scan of the counts gives each
+// atom's local start, and one global atomic per atom with entries reserves a contiguous range of
+// that atom's list.  The entries are staged in LDS grouped by atom, then written out in staging
+// order: each atom's run of the block's entries goes out as consecutive stores (scattered 4-byte
+// stores moved several times their bytes through the caches).
+constexpr int CSC_FILL_SIG = 256;
+__global__ __launch_bounds__(CSC_FILL_SIG) void csc_fill_kernel(const ModDesc* __restrict__ md,
+                                                                const int32_t* __restrict__ ptr,
+                                                                int32_t* __restrict__ fill,
+                                                                int32_t* __restrict__ list_sig,
+                                                                float* __restrict__ list_coef) {
+    constexpr int NT = CSC_FILL_SIG;
+    constexpr int AP = SMDL_MAX_K / NT;          // atoms per thread in the scan
     const ModDesc d = md[blockIdx.y];
-    __shared__ int32_t base[SMDL_MAX_K];
-    __shared__ int32_t cur[SMDL_MAX_K];
-    const int tid = threadIdx.x;
-    for (int a = tid; a < d.K; a += 256) cur[a] = 0;
-    __syncthreads();
-    const int64_t n0 = (int64_t)blockIdx.x * CSC_SIG, n1 = min(d.n, n0 + CSC_SIG);
-    for (int64_t n = n0 + tid; n < n1; n += 256) {
-        const int k = clamp_nnz(d.nnz[n], d.s_stride);
-        for (int i = 0; i < k; ++i) {
-            const int ix = d.idx[n * d.s_stride + i];
-            if (ix >= 0 && ix < d.K) atomicAdd(&cur[ix], 1);
+    __shared__ int32_t cnt[SMDL_MAX_K];          // entries per atom, then the atom's local start
+    __shared__ int32_t gpos[SMDL_MAX_K];         // list position of the atom's first entry
+    __shared__ int32_t wsum[NT / 64];
+    __shared__ int32_t st_sig[NT * SMDL_MAX_S];
+    __shared__ float st_coef[NT * SMDL_MAX_S];
+    __shared__ uint16_t st_atom[NT * SMDL_MAX_S];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int a = tid; a < SMDL_MAX_K; a += NT) cnt[a] = 0;
+    // this thread's signal and its entries (at most SMDL_MAX_S)
+    const int64_t n = (int64_t)blockIdx.x * NT + tid;
+    const int k = n < d.n ? clamp_nnz(d.nnz[n], min(d.s_stride, SMDL_MAX_S)) : 0;
+    int ix[SMDL_MAX_S];
+    float cf[SMDL_MAX_S];
+#pragma unroll
+    for (int i = 0; i < SMDL_MAX_S; ++i) {
+        ix[i] = -1;
+        cf[i] = 0.f;
+        if (i < k) {
+            ix[i] = d.idx[n * d.s_stride + i];
+            cf[i] = d.coef[n * d.s_stride + i];
         }
     }
     __syncthreads();
-    for (int a = tid; a < d.K; a += 256) {
-        const int c = cur[a];
-        base[a] = c ? ptr[d.atom0 + a] + atomicAdd(&fill[d.atom0 + a], c) : 0;
-        cur[a] = 0;
+    int rank[SMDL_MAX_S];
+#pragma unroll
+    for (int i = 0; i < SMDL_MAX_S; ++i) {
+        const bool ok = i < k && ix[i] >= 0 && ix[i] < d.K;
+        rank[i] = ok ? atomicAdd(&cnt[ix[i]], 1) : -1;
     }
     __syncthreads();
-    for (int64_t n = n0 + tid; n < n1; n += 256) {
-        const int k = clamp_nnz(d.nnz[n], d.s_stride);
-        for (int i = 0; i < k; ++i) {
-            const int ix = d.idx[n * d.s_stride + i];
-            if (ix < 0 || ix >= d.K) continue;
-            const int pos = base[ix] + atomicAdd(&cur[ix], 1);
-            list_sig[pos] = (int32_t)n;
-            list_coef[pos] = d.coef[n * d.s_stride + i];
+    // reserve the ranges; exclusive scan of the counts (thread t: atoms AP t .. AP t + AP - 1)
+    int c[AP], run = 0;
+#pragma unroll
+    for (int q = 0; q < AP; ++q) {
+        const int a = AP * tid + q;
+        c[q] = cnt[a];
+        if (a < d.K && c[q] > 0) gpos[a] = ptr[d.atom0 + a] + atomicAdd(&fill[d.atom0 + a], c[q]);
+        run += c[q];
+    }
+    int inc = run;                               // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += v;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int base = inc - run;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+#pragma unroll
+    for (int q = 0; q < AP; ++q) {
+        cnt[AP * tid + q] = base;
+        base += c[q];
+    }
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SMDL_MAX_S; ++i) {
+        if (rank[i] >= 0) {
+            const int p = cnt[ix[i]] + rank[i];
+            st_sig[p] = (int32_t)n;
+            st_coef[p] = cf[i];
+            st_atom[p] = (uint16_t)ix[i];
         }
+    }
+    __syncthreads();
+    for (int p = tid; p < total; p += NT) {
+        const int a = st_atom[p];
+        const int dst = gpos[a] + (p - cnt[a]);
+        list_sig[dst] = st_sig[p];
+        list_coef[dst] = st_coef[p];
     }
 }
 
@@ -1212,7 +1263,8 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
         hipLaunchKernelGGL(csc_fill_fixed_kernel, dim3(csc_blocks, n_desc), dim3(64), 0, st, dev_desc, bbase,
                            total_atoms, list_sig, list_coef);
     } else {
-        hipLaunchKernelGGL(csc_fill_kernel, dim3(csc_blocks, n_desc), dim3(256), 0, st, dev_desc, ptr,
+        const unsigned fill_blocks = (unsigned)std::max<int64_t>(1, (max_n + CSC_FILL_SIG - 1) / CSC_FILL_SIG);
+        hipLaunchKernelGGL(csc_fill_kernel, dim3(fill_blocks, n_desc), dim3(CSC_FILL_SIG), 0, st, dev_desc, ptr,
                            fill, list_sig, list_coef);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
