@@ -37,6 +37,20 @@ void* smdl_ctx::ws(const char* name, size_t bytes) {
     return b.p;
 }
 
+hipError_t smdl_ctx::upload(void* dst, const void* src, size_t bytes) {
+    // the bytes of copies the stream has passed are released (never while a graph is captured)
+    if (!keep.empty()) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone &&
+            hipStreamQuery(stream) == hipSuccess)
+            keep.clear();
+        (void)hipGetLastError();   // the query's not-ready status is no launch error
+    }
+    const uint8_t* b = static_cast<const uint8_t*>(src);
+    keep.emplace_back(b, b + bytes);
+    return hipMemcpyAsync(dst, keep.back().data(), bytes, hipMemcpyHostToDevice, stream);
+}
+
 smdl_status smdl_ctx::fail(smdl_status s, const std::string& msg) {
     err = msg;
     return s;
@@ -255,12 +269,9 @@ smdl_status prepare_sets(smdl_t h, int m, std::vector<SetSpec>& sets, const char
     if (!plan.pack_desc || !plan.gram_desc || !plan.omp_desc)
         return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     smdl_status st;
-    if ((st = h->hip(hipMemcpyAsync(plan.pack_desc, pd.data(), pd.size() * sizeof(PackDesc),
-                                    hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK) return st;
-    if ((st = h->hip(hipMemcpyAsync(plan.gram_desc, gd.data(), gd.size() * sizeof(GramDesc),
-                                    hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK) return st;
-    if ((st = h->hip(hipMemcpyAsync(plan.omp_desc, od.data(), od.size() * sizeof(OmpDesc),
-                                    hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK) return st;
+    if ((st = h->hip(h->upload(plan.pack_desc, pd.data(), pd.size() * sizeof(PackDesc)), "upload")) != SMDL_OK) return st;
+    if ((st = h->hip(h->upload(plan.gram_desc, gd.data(), gd.size() * sizeof(GramDesc)), "upload")) != SMDL_OK) return st;
+    if ((st = h->hip(h->upload(plan.omp_desc, od.data(), od.size() * sizeof(OmpDesc)), "upload")) != SMDL_OK) return st;
     plan.host_desc = od;
     plan.queue = (int*)h->ws((t + ".queue").c_str(), 64);
     if (!plan.queue) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
@@ -285,8 +296,7 @@ smdl_status build_items(smdl_t h, const std::vector<SetSpec>& sets, int T, const
     plan.items = (OmpItem*)h->ws((t + ".items").c_str(), std::max<size_t>(1, items.size()) * sizeof(OmpItem));
     if (!plan.items) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     if (!items.empty())
-        return h->hip(hipMemcpyAsync(plan.items, items.data(), items.size() * sizeof(OmpItem),
-                                     hipMemcpyHostToDevice, h->stream), "upload");
+        return h->hip(h->upload(plan.items, items.data(), items.size() * sizeof(OmpItem)), "upload");
     return SMDL_OK;
 }
 
@@ -511,8 +521,7 @@ smdl_status prepare_mod(smdl_t h, int m, const std::vector<ModSpec>& specs, cons
         atom0 += s.K;
     }
     plan.host_desc = md;
-    smdl_status st = h->hip(hipMemcpyAsync(plan.desc, md.data(), md.size() * sizeof(ModDesc),
-                                           hipMemcpyHostToDevice, h->stream), "upload");
+    smdl_status st = h->hip(h->upload(plan.desc, md.data(), md.size() * sizeof(ModDesc)), "upload");
     if (st != SMDL_OK) return st;
     return h->hip(launch_zero_i32(plan.status, 8 * (int64_t)specs.size(), h->stream), "zero");
 }
@@ -610,8 +619,7 @@ smdl_status learn_sets(smdl_t h, int m, std::vector<SetSpec>& sets, int iters, c
         }
         void* dd = h->ws((t + ".init").c_str(), idd.size() * sizeof(InitDesc));
         if (!dd) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
-        if ((st = h->hip(hipMemcpyAsync(dd, idd.data(), idd.size() * sizeof(InitDesc), hipMemcpyHostToDevice,
-                                        h->stream), "upload")) != SMDL_OK) return st;
+        if ((st = h->hip(h->upload(dd, idd.data(), idd.size() * sizeof(InitDesc)), "upload")) != SMDL_OK) return st;
         if ((st = h->hip(launch_init_from_columns_batched(dd, (int)sets.size(), maxK, m, h->stream), "init")) != SMDL_OK)
             return st;
     }
@@ -825,9 +833,9 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
         return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     std::vector<int64_t> aoff(L + 1, 0);
     for (int t = 0; t < L; ++t) aoff[t + 1] = aoff[t] + sub->K_local[t];
-    if ((st = h->hip(hipMemcpyAsync(offs_dev, sub->offsets, (L + 1) * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK)
+    if ((st = h->hip(h->upload(offs_dev, sub->offsets, (L + 1) * 8), "upload")) != SMDL_OK)
         return st;
-    if ((st = h->hip(hipMemcpyAsync(aoff_dev, aoff.data(), (L + 1) * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK)
+    if ((st = h->hip(h->upload(aoff_dev, aoff.data(), (L + 1) * 8), "upload")) != SMDL_OK)
         return st;
 
     // step 2: local dictionaries
@@ -881,7 +889,7 @@ extern "C" smdl_status smdl_split_merge_learn(smdl_t h, const float* Y, int m, i
         float* minit = (float*)h->ws("sm.minit", (size_t)K * m * 4);
         int32_t* bad = (int32_t*)h->ws("sm.mbad", 64);
         if (!cols || !minit || !bad) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
-        if ((st = h->hip(hipMemcpyAsync(cols, pc.data(), (size_t)K * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK ||
+        if ((st = h->hip(h->upload(cols, pc.data(), (size_t)K * 8), "upload")) != SMDL_OK ||
             (st = h->hip(launch_zero_i32(bad, 1, h->stream), "zero")) != SMDL_OK ||
             (st = h->hip(launch_gather_columns(Ytil, cols, K, sumK, m, minit, bad, h->stream), "merge start")) != SMDL_OK)
             return st;
@@ -964,9 +972,9 @@ extern "C" smdl_status smdl_compose_codes(smdl_t h, int64_t N, const smdl_subset
     if (!offs_dev || !aoff_dev || !sc_dev || !bad) return h->fail(SMDL_E_NOMEM, "workspace allocation failed");
     smdl_status st;
     if ((st = h->hip(launch_zero_i32(bad, 1, h->stream), "zero")) != SMDL_OK) return st;
-    if ((st = h->hip(hipMemcpyAsync(offs_dev, sub->offsets, (L + 1) * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK ||
-        (st = h->hip(hipMemcpyAsync(aoff_dev, aoff.data(), (L + 1) * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK ||
-        (st = h->hip(hipMemcpyAsync(sc_dev, scales, (size_t)L * 8, hipMemcpyHostToDevice, h->stream), "upload")) != SMDL_OK)
+    if ((st = h->hip(h->upload(offs_dev, sub->offsets, (L + 1) * 8), "upload")) != SMDL_OK ||
+        (st = h->hip(h->upload(aoff_dev, aoff.data(), (L + 1) * 8), "upload")) != SMDL_OK ||
+        (st = h->hip(h->upload(sc_dev, scales, (size_t)L * 8), "upload")) != SMDL_OK)
         return st;
     if ((st = h->hip(launch_compose_codes(X1.idx, X1.coef, X1.nnz, X1.s_max, Z.idx, Z.coef, Z.nnz, Z.s_max, offs_dev,
                                           aoff_dev, L, sc_dev, sub->perm, N, K, X_out.idx, X_out.coef, X_out.nnz,

@@ -1,6 +1,7 @@
 // Host-side internals of libsmdl shared by the API translation units.
 #pragma once
 
+#include <cstdint>
 #include <map>
 #include <utility>
 #include <string>
@@ -58,7 +59,13 @@ struct smdl_ctx {
     hipEvent_t ev_prop[4] = {nullptr, nullptr, nullptr, nullptr};
     float prop_ms[3] = {0.f, 0.f, 0.f};
 
+    // Host-to-device copy on the stream of host data the caller may release at once: the bytes
+    // are first copied into `keep`, held until a later upload finds the stream past them, so the
+    // copy never depends on when the runtime reads its source (asynchronous calls return first).
+    std::vector<std::vector<uint8_t>> keep;
+
     void* ws(const char* name, size_t bytes);
+    hipError_t upload(void* dst, const void* src, size_t bytes);
     smdl_status fail(smdl_status s, const std::string& msg);
     smdl_status hip(hipError_t e, const char* what);
 };
