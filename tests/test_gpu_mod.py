@@ -126,6 +126,40 @@ def test_mod_unused_atoms_and_ridge(h, dev, solver):
     assert np.linalg.norm(Dn[:2] - Dref[:2], axis=1).max() <= 1e-3
 
 
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_mod_concentrated_lists(h, dev, deterministic):
+    """Every code holds the same 12 atoms (in shuffled slots) plus 4 of a pool of 40, some codes
+    shorter than their stride: lists of 3000 entries for the shared atoms, runs of up to 256 of one
+    atom in a block of the list transpose, each atom's range filled by many blocks, a ragged last
+    block.  Teacher-forced against the oracle's MOD, in both list modes."""
+    import paper_1403_4781_amd as smdl
+    print(f"case mod concentrated lists deterministic={deterministic}", flush=True)
+    rng = np.random.default_rng(3200)
+    m, K, N, S = 64, 256, 3000, 16
+    Y = rng.standard_normal((N, m)).astype(np.float32)
+    idx = np.full((N, S), -1, np.int32)
+    coef = np.zeros((N, S))
+    nnz = np.where(np.arange(N) % 7 == 0, 13, S).astype(np.int32)
+    for n in range(N):
+        sup = np.concatenate([np.arange(12), 100 + rng.choice(40, 4, replace=False)])
+        rng.shuffle(sup)
+        idx[n, :nnz[n]] = sup[:nnz[n]]
+        coef[n, :nnz[n]] = rng.standard_normal(nnz[n])
+    codes = oracle.Codes(idx, coef.astype(np.float32).astype(np.float64), nnz)
+    D = synth.gaussian_dictionary(rng, m, K).astype(np.float32)
+    Dref, nu_ref, _ = oracle.mod_update(Y, codes, D)
+    Dg = _t(D, dev)
+    h.set_flags(smdl.SMDL_DETERMINISTIC if deterministic else 0)
+    try:
+        nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+    finally:
+        h.set_flags(0)
+    err = np.linalg.norm(Dg.cpu().numpy() - Dref, axis=1).max()
+    print(f"  max atom error {err:.3e} unused {nu}/{nu_ref}", flush=True)
+    assert nu == nu_ref == K - 52
+    assert err <= D_TOL
+
+
 def test_mod_solver_mode_checked(h):
     import paper_1403_4781_amd as smdl
     print("case mod solver mode", flush=True)
