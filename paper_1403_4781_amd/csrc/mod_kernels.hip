@@ -131,28 +131,75 @@ __global__ __launch_bounds__(64) void csc_fill_fixed_kernel(const ModDesc* __res
     }
 }
 
-// Exclusive scan of cnt[0..total) into ptr[0..total]; single block of 1024 threads.
+// Exclusive scan of cnt[0..total) into ptr[0..total]; single block of 1024 threads.  Wave w
+// owns the contiguous chunk [w C, (w + 1) C), C = 64 r, read as r rows of 64 consecutive entries
+// (coalesced; all r loads issued at once when r <= SCAN_CAP, else row after row): each row is
+// scanned across the wave with shuffles and the row totals carried; one barrier then adds the
+// totals of the earlier waves.
+constexpr int SCAN_CAP = 64;
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
 __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ cnt, int total,
                                                     int32_t* __restrict__ ptr) {
-    __shared__ int32_t part[1024];
-    const int per = (total + 1023) / 1024;
-    const int b = threadIdx.x * per, e = min(total, b + per);
-    int32_t s = 0;
-    for (int i = b; i < e; ++i) s += cnt[i];
-    part[threadIdx.x] = s;
+    __shared__ int32_t wtot[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = (total + 1023) / 1024;                 // rows of 64 per wave
+    const int64_t c0 = (int64_t)wave * 64 * r;
+    int32_t carry = 0;
+    int32_t v[SCAN_CAP];
+    if (r <= SCAN_CAP) {
+#pragma unroll
+        for (int i = 0; i < SCAN_CAP; ++i) {
+            const int64_t k = c0 + 64 * i + lane;
+            v[i] = (i < r && k < total) ? cnt[k] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < SCAN_CAP; ++i) {
+            if (i < r) {
+                const int32_t inc = wave_incl_scan(v[i], lane);
+                const int32_t tot = __shfl(inc, 63, 64);
+                v[i] = carry + inc - v[i];               // exclusive, within the wave's chunk
+                carry += tot;
+            }
+        }
+    } else {
+        for (int i = 0; i < r; ++i) {
+            const int64_t k = c0 + 64 * i + lane;
+            const int32_t x = k < total ? cnt[k] : 0;
+            carry += __shfl(wave_incl_scan(x, lane), 63, 64);
+        }
+    }
+    if (lane == 0) wtot[wave] = carry;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    int32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += wtot[w];
+    if (r <= SCAN_CAP) {
+#pragma unroll
+        for (int i = 0; i < SCAN_CAP; ++i) {
+            const int64_t k = c0 + 64 * i + lane;
+            if (i < r && k < total) ptr[k] = base + v[i];
+        }
+    } else {
+        int32_t run = base;
+        for (int i = 0; i < r; ++i) {
+            const int64_t k = c0 + 64 * i + lane;
+            const int32_t x = k < total ? cnt[k] : 0;
+            const int32_t inc = wave_incl_scan(x, lane);
+            if (k < total) ptr[k] = run + inc - x;
+            run += __shfl(inc, 63, 64);
+        }
     }
-    int32_t run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
-    for (int i = b; i < e; ++i) {
-        ptr[i] = run;
-        run += cnt[i];
+    if (threadIdx.x == 1023) {
+        int32_t all = 0;
+        for (int w = 0; w < 16; ++w) all += wtot[w];
+        ptr[total] = all;
     }
-    if (threadIdx.x == 1023) ptr[total] = part[1023];
 }
 
 // Each block takes CSC_FILL_SIG signals, one per thread.  One LDS atomic per entry counts the
