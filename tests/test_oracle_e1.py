@@ -9,6 +9,19 @@ import oracle
 from paper_1403_4781_amd import evaluate, synth
 
 
+def _table1():
+    """Table 1's printed values (Section 3.1), from tests/golden/table1_synthetic.txt."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_synthetic.txt")
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                key, a, b = line.split()
+                out[key] = (float(a), float(b))
+    return out
+
+
 def test_atom_recovery_closed_forms():
     rng = np.random.default_rng(501)
     D = synth.gaussian_dictionary(rng, 30, 60)
@@ -69,3 +82,13 @@ def test_e1_oracle_table1_ordering():
     assert std_db < sm_db - 3.0
     assert std_rec > sm_rec
     assert std_rec >= 0.9 and sm_rec >= 0.6
+    # against the averages Table 1 prints (tests/golden/table1_synthetic.txt): one seeded trial
+    # has the table's gap in the training error (same sign, within a factor of 2) and lies within
+    # the trial-to-trial spread of its averages: 4 dB and 20 points of recovery, about 2.5
+    # standard deviations of 20 trials of this experiment (2.6 dB, 8 points)
+    tab = _table1()
+    gap, gap_paper = std_db - sm_db, tab["mse_train_db"][0] - tab["mse_train_db"][1]
+    assert gap_paper < 0 and 0.5 * gap_paper >= gap >= 2.0 * gap_paper
+    assert abs(std_db - tab["mse_train_db"][0]) <= 4.0 and abs(sm_db - tab["mse_train_db"][1]) <= 4.0
+    assert abs(100 * std_rec - tab["atom_recovery_percent"][0]) <= 20
+    assert abs(100 * sm_rec - tab["atom_recovery_percent"][1]) <= 20
