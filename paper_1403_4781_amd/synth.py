@@ -61,7 +61,11 @@ def sparse_signals(rng: np.random.Generator, D0: np.ndarray, s0: int, sigma: flo
     val = np.empty((N, s0), dtype=np.float64)
     for b0 in range(0, N, block):
         B = min(block, N - b0)
-        order = np.argsort(rng.random((B, K0)), axis=1)[:, :s0]
+        # the first s0 of a random ordering: the s0 smallest of K0 uniforms, in increasing order
+        # (selected by a partition, then sorted among themselves)
+        r = rng.random((B, K0))
+        part = np.argpartition(r, s0 - 1, axis=1)[:, :s0] if s0 < K0 else np.argsort(r, axis=1)
+        order = np.take_along_axis(part, np.argsort(np.take_along_axis(r, part, axis=1), axis=1), axis=1)
         w = rng.standard_normal((B, s0))
         noise = rng.standard_normal((B, m))
         # y_n = sum_i w_i d_{order_i} + sigma * noise  (generation only)
