@@ -14,7 +14,7 @@ import torch
 
 import oracle
 from paper_1403_4781_amd import synth
-from tests.parity import correlation_network, proposer_parity, to_np
+from tests.parity import compare, correlation_network, proposed_oracle, proposer_parity, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -257,6 +257,50 @@ def test_proposer_network_at_benchmark_shape(h, dev):
             e = _relfro(gpu.astype(np.float64).ravel() - w0.astype(np.float64).ravel(), w - w0.astype(np.float64).ravel())
             print(f"  layer {l} update rel {e:.2e}", flush=True)
             assert e <= 0.05     # Adam's first step is ~lr*sign(g): a tiny |g| may flip sign
+    p.close()
+
+
+def test_proposed_path_full_size_sampled(h, dev):
+    """The learned-proposal path at the benchmark's evaluation size (100000 signals, m=64, K=256,
+    s=8, 24 candidates), in the launch configuration the benchmark times: the network on 64-row
+    work groups, the top-k, the restricted OMP and the fallback list coded by the full kernel.
+    The correlation network (logits |d_k^T y| / ||y||) keeps a share of restricted codes.  400
+    sampled signals against the oracle: the candidates (away from a top-24 logit boundary), the
+    fallback decisions and the codes."""
+    g = synth.rng_streams(4020)
+    D = synth.gaussian_dictionary(g[0], 64, 256).astype(np.float32)
+    Y, _, _ = synth.sparse_signals(g[1], D.astype(np.float64), 8, 0.02, 100000)
+    # the fallback threshold from the oracle's plain codes of 2000 other signals
+    Yc, _, _ = synth.sparse_signals(g[2], D.astype(np.float64), 8, 0.02, 2000)
+    eps_fb = 1.1 * float(np.sqrt(np.mean(oracle.omp(D, Yc, 8).res_norm ** 2)))
+    Wc, bc = correlation_network(D)
+    p = h.proposer(Wc, bc)
+    rs = np.sort(np.random.default_rng(4021).choice(100000, 400, replace=False))
+    lg = oracle.mlp_forward(Wc, bc, Y[rs])
+    srt = -np.sort(-lg, axis=1)
+    boundary = (srt[:, 23] - srt[:, 24]) < 1e-3 * np.maximum(np.abs(srt[:, 23]), 1.0)
+    for mult in (1.0, 3.0):
+        # the benchmark's threshold (1.1x the plain residual), and a looser one that keeps many
+        # restricted codes
+        eps = mult * eps_fb
+        print(f"case proposed full size N=100000, threshold x{1.1 * mult:.1f}", flush=True)
+        X, fb, nfb, cand = h.omp_code_proposed(p, _t(D, dev), _t(Y, dev), 8, 24, eps, want_cand=True)
+        gi, gc, gn = to_np(X)
+        cn = cand.cpu().numpy()
+        fbg = fb.cpu().numpy().astype(bool)
+        print(f"  fallbacks {nfb} of 100000; restricted codes in the sample {int((~fbg[rs]).sum())}", flush=True)
+        assert nfb == int(fbg.sum()) and 0 < nfb < 100000
+        ora_c = oracle.propose_code(D, Y[rs], lg, 24, 8, eps)
+        same_c = (cn[rs] == ora_c.cand).all(axis=1)
+        print(f"  candidates agree {same_c[~boundary].mean():.5f} (logit-boundary signals {boundary.sum()})",
+              flush=True)
+        assert same_c[~boundary].mean() >= 0.999
+        ora, fell, dtie = proposed_oracle(D, Y[rs], cn[rs], 8, eps)
+        assert (fbg[rs] == fell)[~dtie].all()
+        compare((gi[rs], gc[rs], gn[rs]), ora, D, Y[rs], label=f"proposed N=1e5 sampled x{mult}",
+                ties=oracle.tie_mask(ora) | dtie)
+        if mult > 1.0:
+            assert (~fbg[rs]).sum() >= 40
     p.close()
 
 
