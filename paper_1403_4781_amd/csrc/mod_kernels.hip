@@ -291,6 +291,10 @@ __global__ __launch_bounds__(CSC_FILL_SIG) void csc_fill_kernel(const ModDesc* _
     }
 }
 
+// mod_products_kernel's LDS: the A column, the B row sums and the staged list entries.
+constexpr int MP_STAGE = 512;                // list entries staged per pass
+constexpr int MP_LDS = SMDL_MAX_K * 8 + 256 * 8 + MP_STAGE * 8;
+
 // One block per (atom a, descriptor, chunk c): the products over chunk c of the P equal parts of
 // atom a's list.  Chunk 0 writes column a of M = [A; B] (FP64) in place; chunk c > 0 writes the
 // same column of copy c - 1 of the M arena in `part` (sum_reduce_kernel adds the copies in a
@@ -306,10 +310,10 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
     const int c = blockIdx.z, P = gridDim.z;
     if (a >= d.Kpad) return;
     static_assert(SMDL_MAX_S <= 16, "16 support slots per list entry");
-    constexpr int PSTAGE = 512;              // list entries staged per pass
+    constexpr int PSTAGE = MP_STAGE;
     constexpr int PB = 8;                    // signal loads in flight per thread
     __shared__ double colA[SMDL_MAX_K];
-    __shared__ double partB[8][SMDL_MAX_M];
+    __shared__ double partB[256];            // groups x mcov = 256 row sums
     __shared__ int32_t s_sig[PSTAGE];
     __shared__ float s_cf[PSTAGE];
     const int tid = threadIdx.x;
@@ -398,15 +402,15 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
                 for (; q < cnt; q += groups) acc += (double)s_cf[q] * (double)d.Y[(int64_t)s_sig[q] * m + r];
             }
         }
-        partB[grp][r] = acc;
+        partB[grp * mcov + r] = acc;
     } else {
-        partB[grp][r] = 0.0;
+        partB[grp * mcov + r] = 0.0;
     }
     __syncthreads();
     for (int l = tid; l < d.Kpad; l += 256) out[l] = colA[l];
     for (int rr = tid; rr < m; rr += 256) {
         double sm = 0.0;
-        for (int q = 0; q < groups; ++q) sm += partB[q][rr];
+        for (int q = 0; q < groups; ++q) sm += partB[q * mcov + rr];
         out[d.Kpad + rr] = sm;
     }
 }
@@ -1315,7 +1319,14 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
                            fill, list_sig, list_coef);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(mod_products_kernel, dim3(max_kpad, n_desc, chunks), dim3(256), 0, st, dev_desc, m, ptr,
+    // The kernel fits 8 blocks per CU (14 KB of LDS each).  When a dictionary's signals exceed an
+    // XCD's 4 MB L2, fewer blocks in flight gather from fewer dictionaries at once: unused dynamic
+    // LDS caps the launch at 6 blocks per CU (at m=256 and 10^4 signals per dictionary 5 % faster
+    // than 8 blocks; 3, 4 and 5 blocks are slower than 6).
+    static_assert(8 * MP_LDS <= 160 * 1024, "8 blocks of mod_products_kernel per CU");
+    const bool mp_cap = (int64_t)max_n * m * 4 > ((int64_t)4 << 20);
+    const unsigned mp_pad = mp_cap ? (unsigned)(160 * 1024 / 6 - 1024 - MP_LDS) : 0u;
+    hipLaunchKernelGGL(mod_products_kernel, dim3(max_kpad, n_desc, chunks), dim3(256), mp_pad, st, dev_desc, m, ptr,
                        list_sig, list_coef, arena, part, arena_len, fixed ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (chunks > 1) {
