@@ -42,13 +42,13 @@ constexpr int CSC_SIG = 1024;
 
 __global__ __launch_bounds__(256) void csc_count_kernel(const ModDesc* __restrict__ md, int32_t* __restrict__ cnt,
                                                         int32_t* __restrict__ status, int32_t* __restrict__ bcnt,
-                                                        int total_atoms) {
+                                                        int total_atoms, int spb) {
     const ModDesc d = md[blockIdx.y];
     __shared__ int32_t hist[SMDL_MAX_K];
     const int tid = threadIdx.x;
     for (int a = tid; a < d.K; a += 256) hist[a] = 0;
     __syncthreads();
-    const int64_t n0 = (int64_t)blockIdx.x * CSC_SIG, n1 = min(d.n, n0 + CSC_SIG);
+    const int64_t n0 = (int64_t)blockIdx.x * spb, n1 = min(d.n, n0 + (int64_t)spb);
     bool bad = false;
     for (int64_t n = n0 + tid; n < n1; n += 256) {
         const int k0 = d.nnz[n];
@@ -79,55 +79,6 @@ __global__ void csc_block_base_kernel(const int32_t* __restrict__ ptr, const int
     for (int b = 0; b < nblk; ++b) {
         bbase[(int64_t)b * total_atoms + ga] = run;
         run += bcnt[(int64_t)b * total_atoms + ga];
-    }
-}
-
-// Fixed-order mode: one wave per block of CSC_SIG signals places the block's entries from its
-// bases in a fixed order (chunks of 64 signals, within a chunk slot by slot, within a slot by
-// signal): the lanes holding the same atom take consecutive positions by lane order (ballot and
-// rank), one atom per round.  The lists, and so the order of every product sum, are then the
-// same on every run.
-__global__ __launch_bounds__(64) void csc_fill_fixed_kernel(const ModDesc* __restrict__ md,
-                                                            const int32_t* __restrict__ bbase, int total_atoms,
-                                                            int32_t* __restrict__ list_sig,
-                                                            float* __restrict__ list_coef) {
-    const ModDesc d = md[blockIdx.y];
-    __shared__ int32_t cur[SMDL_MAX_K];
-    const int lane = threadIdx.x;
-    for (int a = lane; a < d.K; a += 64) cur[a] = bbase[(int64_t)blockIdx.x * total_atoms + d.atom0 + a];
-    __syncthreads();
-    const int64_t n0 = (int64_t)blockIdx.x * CSC_SIG, n1 = min(d.n, n0 + CSC_SIG);
-    const uint64_t lower = (1ull << lane) - 1ull;
-    for (int64_t nb = n0; nb < n1; nb += 64) {
-        const int64_t n = nb + lane;
-        const bool valid = n < n1;
-        const int k = valid ? clamp_nnz(d.nnz[n], d.s_stride) : 0;
-        for (int i = 0; i < d.s_stride; ++i) {
-            int ix = -1;
-            float cf = 0.f;
-            if (i < k) {
-                ix = d.idx[n * d.s_stride + i];
-                cf = d.coef[n * d.s_stride + i];
-            }
-            bool todo = ix >= 0 && ix < d.K;
-            for (;;) {
-                const uint64_t act = __ballot(todo);
-                if (!act) break;
-                const int first = __builtin_ctzll(act);
-                const int u = __shfl(ix, first, 64);
-                const bool mine = todo && ix == u;
-                const uint64_t grp = __ballot(mine);
-                const int base = cur[u];
-                if (mine) {
-                    const int pos = base + __popcll(grp & lower);
-                    list_sig[pos] = (int32_t)n;
-                    list_coef[pos] = cf;
-                    todo = false;
-                }
-                if (lane == 0) cur[u] = base + __popcll(grp);
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
     }
 }
 
@@ -208,14 +159,24 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ 
 // that atom's list.  The entries are staged in LDS grouped by atom, then written out in staging
 // order: each atom's run of the block's entries goes out as consecutive stores (scattered 4-byte
 // stores moved several times their bytes through the caches).
+// Fixed-order mode (FIXED): the entries are ranked slot by slot, and within a slot by signal.
+// In slot i each signal has at most one entry; it sets its bit in its atom's 256-bit mask (an
+// LDS OR, whose result does not depend on the order of the ORs), and its rank is the atom's
+// entries of the earlier slots plus the set bits below its own.  The block's run of each atom
+// starts at bbase (the atom's list start plus the entries of the earlier blocks, from the
+// per-block counts), so the lists are the same on every run.
 constexpr int CSC_FILL_SIG = 256;
+template <bool FIXED>
 __global__ __launch_bounds__(CSC_FILL_SIG) void csc_fill_kernel(const ModDesc* __restrict__ md,
                                                                 const int32_t* __restrict__ ptr,
                                                                 int32_t* __restrict__ fill,
+                                                                const int32_t* __restrict__ bbase,
+                                                                int total_atoms,
                                                                 int32_t* __restrict__ list_sig,
                                                                 float* __restrict__ list_coef) {
     constexpr int NT = CSC_FILL_SIG;
     constexpr int AP = SMDL_MAX_K / NT;          // atoms per thread in the scan
+    constexpr int MW = NT / 32;                  // mask words per atom (fixed-order mode)
     const ModDesc d = md[blockIdx.y];
     __shared__ int32_t cnt[SMDL_MAX_K];          // entries per atom, then the atom's local start
     __shared__ int32_t gpos[SMDL_MAX_K];         // list position of the atom's first entry
@@ -223,8 +184,11 @@ __global__ __launch_bounds__(CSC_FILL_SIG) void csc_fill_kernel(const ModDesc* _
     __shared__ int32_t st_sig[NT * SMDL_MAX_S];
     __shared__ float st_coef[NT * SMDL_MAX_S];
     __shared__ uint16_t st_atom[NT * SMDL_MAX_S];
+    __shared__ uint32_t amask[FIXED ? SMDL_MAX_K * MW : 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int a = tid; a < SMDL_MAX_K; a += NT) cnt[a] = 0;
+    if constexpr (FIXED)
+        for (int w = tid; w < SMDL_MAX_K * MW; w += NT) amask[w] = 0u;
     // this thread's signal and its entries (at most SMDL_MAX_S)
     const int64_t n = (int64_t)blockIdx.x * NT + tid;
     const int k = n < d.n ? clamp_nnz(d.nnz[n], min(d.s_stride, SMDL_MAX_S)) : 0;
@@ -241,10 +205,41 @@ __global__ __launch_bounds__(CSC_FILL_SIG) void csc_fill_kernel(const ModDesc* _
     }
     __syncthreads();
     int rank[SMDL_MAX_S];
+    if constexpr (FIXED) {
+        const int S = min(d.s_stride, SMDL_MAX_S);   // the same for the whole block
+        const int wd = tid >> 5;
+        const uint32_t bit = 1u << (tid & 31);
 #pragma unroll
-    for (int i = 0; i < SMDL_MAX_S; ++i) {
-        const bool ok = i < k && ix[i] >= 0 && ix[i] < d.K;
-        rank[i] = ok ? atomicAdd(&cnt[ix[i]], 1) : -1;
+        for (int i = 0; i < SMDL_MAX_S; ++i) {
+            rank[i] = -1;
+            if (i >= S) continue;
+            const bool ok = i < k && ix[i] >= 0 && ix[i] < d.K;
+            if (ok) atomicOr(&amask[ix[i] * MW + wd], bit);
+            __syncthreads();
+            int tot = 0;
+            bool lead = false;
+            if (ok) {
+                const uint32_t* mk = &amask[ix[i] * MW];
+                int below = __popc(mk[wd] & (bit - 1u));
+                for (int w = 0; w < wd; ++w) below += __popc(mk[w]);
+                rank[i] = cnt[ix[i]] + below;
+                lead = below == 0;                   // the atom's lowest signal in this slot
+                if (lead)
+                    for (int w = wd; w < MW; ++w) tot += __popc(mk[w]);
+            }
+            __syncthreads();                         // every rank is read
+            if (lead) {
+                cnt[ix[i]] += tot;
+                for (int w = 0; w < MW; ++w) amask[ix[i] * MW + w] = 0u;
+            }
+            __syncthreads();
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < SMDL_MAX_S; ++i) {
+            const bool ok = i < k && ix[i] >= 0 && ix[i] < d.K;
+            rank[i] = ok ? atomicAdd(&cnt[ix[i]], 1) : -1;
+        }
     }
     __syncthreads();
     // reserve the ranges; exclusive scan of the counts (thread t: atoms AP t .. AP t + AP - 1)
@@ -253,7 +248,12 @@ __global__ __launch_bounds__(CSC_FILL_SIG) void csc_fill_kernel(const ModDesc* _
     for (int q = 0; q < AP; ++q) {
         const int a = AP * tid + q;
         c[q] = cnt[a];
-        if (a < d.K && c[q] > 0) gpos[a] = ptr[d.atom0 + a] + atomicAdd(&fill[d.atom0 + a], c[q]);
+        if (a < d.K && c[q] > 0) {
+            if constexpr (FIXED)
+                gpos[a] = bbase[(int64_t)blockIdx.x * total_atoms + d.atom0 + a];
+            else
+                gpos[a] = ptr[d.atom0 + a] + atomicAdd(&fill[d.atom0 + a], c[q]);
+        }
         run += c[q];
     }
     int inc = run;                               // inclusive scan over the wave
@@ -299,12 +299,18 @@ constexpr int MP_LDS = SMDL_MAX_K * 8 + 256 * 8 + MP_STAGE * 8;
 // atom a's list.  Chunk 0 writes column a of M = [A; B] (FP64) in place; chunk c > 0 writes the
 // same column of copy c - 1 of the M arena in `part` (sum_reduce_kernel adds the copies in a
 // fixed order).  Long lists (many signals per atom) are so spread over P blocks.
+// Fixed-order mode (FIXED): the A column is summed in list order without atomics.  Each round
+// takes 16 entries x 16 support slots, one (entry, slot) pair per thread, keyed 16 entry + slot;
+// a pair sets its key's bit in its target atom's 256-bit mask (dynamic LDS, 8 words per atom)
+// and the pair with the lowest key of each target adds the round's values of that target in key
+// order.  B is in list order in both modes.
+template <bool FIXED>
 __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __restrict__ md, int m,
                                                            const int32_t* __restrict__ ptr,
                                                            const int32_t* __restrict__ list_sig,
                                                            const float* __restrict__ list_coef,
                                                            const double* __restrict__ arena, double* __restrict__ part,
-                                                           int64_t arena_len, int fixed_order) {
+                                                           int64_t arena_len) {
     const ModDesc d = md[blockIdx.y];
     const int a = blockIdx.x;
     const int c = blockIdx.z, P = gridDim.z;
@@ -316,8 +322,12 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
     __shared__ double partB[256];            // groups x mcov = 256 row sums
     __shared__ int32_t s_sig[PSTAGE];
     __shared__ float s_cf[PSTAGE];
+    extern __shared__ uint32_t amask[];      // fixed-order mode: Kpad x 8 words
+    __shared__ double vbuf[FIXED ? 256 : 1];
     const int tid = threadIdx.x;
     for (int l = tid; l < d.Kpad; l += 256) colA[l] = 0.0;
+    if constexpr (FIXED)
+        for (int w = tid; w < d.Kpad * 8; w += 256) amask[w] = 0u;
     __syncthreads();
     const int64_t ld = d.Kpad + m;
     double* out = (c == 0 ? d.A : part + (int64_t)(c - 1) * arena_len + (d.A - arena)) + (int64_t)a * ld;
@@ -339,53 +349,67 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
                 s_cf[q] = list_coef[p0 + q];
             }
             __syncthreads();
-            // A column: every entry (n, x_na) adds x_na * x_nl at every atom l of signal n; in the
-            // fixed-order mode one thread adds them in list order
-            auto add_entry = [&](int q, bool atomic) {
-                const int64_t n = s_sig[q];
-                const double xa = s_cf[q];
-                const int k = clamp_nnz(d.nnz[n], d.s_stride);
-                for (int i = 0; i < k; ++i) {
-                    const int l = d.idx[n * d.s_stride + i];
-                    if (l < 0 || l >= d.K) continue;
-                    const double v = xa * (double)d.coef[n * d.s_stride + i];
-                    if (atomic) atomicAdd(&colA[l], v);
-                    else colA[l] += v;
-                }
-            };
-            if (fixed_order) {
-                if (tid == 0)
-                    for (int q = 0; q < cnt; ++q) add_entry(q, false);
-            } else {
-                // lanes over (entry, support slot): 16 entries per pass of the block, the loads
-                // of UA passes issued before their adds (s_stride <= 16 slots per entry)
-                constexpr int UA = 4;
-                const int slot = tid & 15, eq = tid >> 4;
-                for (int q0 = 0; q0 < cnt; q0 += 16 * UA) {
-                    int lv[UA], kv[UA];
-                    float cv[UA];
-                    double xv[UA];
+            // A column: every entry (n, x_na) adds x_na * x_nl at every atom l of signal n; the
+            // block's lanes take (entry, support slot) pairs, 16 entries per round, the loads of
+            // UA rounds issued before their adds (s_stride <= 16 slots per entry)
+            constexpr int UA = 4;
+            const int slot = tid & 15, eq = tid >> 4;
+            for (int q0 = 0; q0 < cnt; q0 += 16 * UA) {
+                int lv[UA], kv[UA];
+                float cv[UA];
+                double xv[UA];
 #pragma unroll
-                    for (int u = 0; u < UA; ++u) {
-                        const int q = q0 + 16 * u + eq;
-                        lv[u] = -1;
-                        kv[u] = 0;
-                        cv[u] = 0.f;
-                        xv[u] = 0.0;
-                        if (q < cnt) {
-                            const int64_t n = s_sig[q];
-                            kv[u] = d.nnz[n];
-                            if (slot < d.s_stride) {
-                                lv[u] = d.idx[n * d.s_stride + slot];
-                                cv[u] = d.coef[n * d.s_stride + slot];
-                            }
-                            xv[u] = s_cf[q];
+                for (int u = 0; u < UA; ++u) {
+                    const int q = q0 + 16 * u + eq;
+                    lv[u] = -1;
+                    kv[u] = 0;
+                    cv[u] = 0.f;
+                    xv[u] = 0.0;
+                    if (q < cnt) {
+                        const int64_t n = s_sig[q];
+                        kv[u] = d.nnz[n];
+                        if (slot < d.s_stride) {
+                            lv[u] = d.idx[n * d.s_stride + slot];
+                            cv[u] = d.coef[n * d.s_stride + slot];
                         }
+                        xv[u] = s_cf[q];
                     }
+                }
 #pragma unroll
-                    for (int u = 0; u < UA; ++u)
-                        if (slot < clamp_nnz(kv[u], d.s_stride) && lv[u] >= 0 && lv[u] < d.K)
-                            atomicAdd(&colA[lv[u]], xv[u] * (double)cv[u]);
+                for (int u = 0; u < UA; ++u) {
+                    const bool ok = slot < clamp_nnz(kv[u], d.s_stride) && lv[u] >= 0 && lv[u] < d.K;
+                    if constexpr (FIXED) {
+                        // one round: mark, then the lowest key of each target adds in key order
+                        const int wd = tid >> 5;
+                        const uint32_t bit = 1u << (tid & 31);
+                        if (ok) {
+                            vbuf[tid] = xv[u] * (double)cv[u];
+                            atomicOr(&amask[lv[u] * 8 + wd], bit);
+                        }
+                        __syncthreads();
+                        bool lead = false;
+                        if (ok) {
+                            const uint32_t* mk = &amask[lv[u] * 8];
+                            lead = (mk[wd] & (bit - 1u)) == 0u;
+                            for (int w = 0; w < wd && lead; ++w) lead = mk[w] == 0u;
+                            if (lead) {
+                                double acc = colA[lv[u]];
+                                for (int w = wd; w < 8; ++w) {
+                                    uint32_t b = mk[w];
+                                    while (b) {
+                                        acc += vbuf[32 * w + __builtin_ctz(b)];
+                                        b &= b - 1u;
+                                    }
+                                }
+                                colA[lv[u]] = acc;
+                            }
+                        }
+                        __syncthreads();             // every mask is read
+                        if (ok) amask[lv[u] * 8 + wd] = 0u;
+                        __syncthreads();
+                    } else {
+                        if (ok) atomicAdd(&colA[lv[u]], xv[u] * (double)cv[u]);
+                    }
                 }
             }
             // B column: rows split over threads, entries over groups of threads, PB signal
@@ -1289,7 +1313,7 @@ static bool mod_solve_multi(int n_desc, int solver) {
     return n_desc < 256;
 }
 
-int64_t mod_csc_blocks(int64_t max_n) { return std::max<int64_t>(1, (max_n + CSC_SIG - 1) / CSC_SIG); }
+int64_t mod_csc_blocks(int64_t max_n) { return std::max<int64_t>(1, (max_n + CSC_FILL_SIG - 1) / CSC_FILL_SIG); }
 
 hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atoms, int64_t max_n, int32_t* cnt,
                       int32_t* fill, int32_t* ptr, int32_t* list_sig, float* list_coef, int32_t* status,
@@ -1301,33 +1325,40 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
     if (fixed && !bbase) return hipErrorInvalidValue;
     if ((e = launch_zero_i32(cnt, total_atoms, st)) != hipSuccess) return e;
     if ((e = launch_zero_i32(fill, total_atoms, st)) != hipSuccess) return e;
+    // the fixed-order mode counts per block of the fill kernel (its run bases come from them)
     const unsigned csc_blocks = (unsigned)std::max<int64_t>(1, (max_n + CSC_SIG - 1) / CSC_SIG);
-    hipLaunchKernelGGL(csc_count_kernel, dim3(csc_blocks, n_desc), dim3(256), 0, st, dev_desc, cnt, status, bcnt,
-                       total_atoms);
+    const unsigned fill_blocks = (unsigned)std::max<int64_t>(1, (max_n + CSC_FILL_SIG - 1) / CSC_FILL_SIG);
+    hipLaunchKernelGGL(csc_count_kernel, dim3(fixed ? fill_blocks : csc_blocks, n_desc), dim3(256), 0, st, dev_desc,
+                       cnt, status, bcnt, total_atoms, fixed ? CSC_FILL_SIG : CSC_SIG);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, cnt, total_atoms, ptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (fixed) {
         hipLaunchKernelGGL(csc_block_base_kernel, dim3((total_atoms + 255) / 256), dim3(256), 0, st, ptr, bcnt, bbase,
-                           total_atoms, (int)csc_blocks);
+                           total_atoms, (int)fill_blocks);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(csc_fill_fixed_kernel, dim3(csc_blocks, n_desc), dim3(64), 0, st, dev_desc, bbase,
-                           total_atoms, list_sig, list_coef);
+        hipLaunchKernelGGL(csc_fill_kernel<true>, dim3(fill_blocks, n_desc), dim3(CSC_FILL_SIG), 0, st, dev_desc, ptr,
+                           fill, bbase, total_atoms, list_sig, list_coef);
     } else {
-        const unsigned fill_blocks = (unsigned)std::max<int64_t>(1, (max_n + CSC_FILL_SIG - 1) / CSC_FILL_SIG);
-        hipLaunchKernelGGL(csc_fill_kernel, dim3(fill_blocks, n_desc), dim3(CSC_FILL_SIG), 0, st, dev_desc, ptr,
-                           fill, list_sig, list_coef);
+        hipLaunchKernelGGL(csc_fill_kernel<false>, dim3(fill_blocks, n_desc), dim3(CSC_FILL_SIG), 0, st, dev_desc, ptr,
+                           fill, (const int32_t*)nullptr, total_atoms, list_sig, list_coef);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // The kernel fits 8 blocks per CU (14 KB of LDS each).  When a dictionary's signals exceed an
     // XCD's 4 MB L2, fewer blocks in flight gather from fewer dictionaries at once: unused dynamic
     // LDS caps the launch at 6 blocks per CU (at m=256 and 10^4 signals per dictionary 5 % faster
-    // than 8 blocks; 3, 4 and 5 blocks are slower than 6).
+    // than 8 blocks; 3, 4 and 5 blocks are slower than 6).  The fixed-order mode's masks take
+    // 32 bytes per atom of dynamic LDS.
     static_assert(8 * MP_LDS <= 160 * 1024, "8 blocks of mod_products_kernel per CU");
-    const bool mp_cap = (int64_t)max_n * m * 4 > ((int64_t)4 << 20);
-    const unsigned mp_pad = mp_cap ? (unsigned)(160 * 1024 / 6 - 1024 - MP_LDS) : 0u;
-    hipLaunchKernelGGL(mod_products_kernel, dim3(max_kpad, n_desc, chunks), dim3(256), mp_pad, st, dev_desc, m, ptr,
-                       list_sig, list_coef, arena, part, arena_len, fixed ? 1 : 0);
+    if (fixed) {
+        hipLaunchKernelGGL(mod_products_kernel<true>, dim3(max_kpad, n_desc, chunks), dim3(256),
+                           (unsigned)max_kpad * 32u, st, dev_desc, m, ptr, list_sig, list_coef, arena, part, arena_len);
+    } else {
+        const bool mp_cap = (int64_t)max_n * m * 4 > ((int64_t)4 << 20);
+        const unsigned mp_pad = mp_cap ? (unsigned)(160 * 1024 / 6 - 1024 - MP_LDS) : 0u;
+        hipLaunchKernelGGL(mod_products_kernel<false>, dim3(max_kpad, n_desc, chunks), dim3(256), mp_pad, st, dev_desc,
+                           m, ptr, list_sig, list_coef, arena, part, arena_len);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (chunks > 1) {
         const unsigned g = (unsigned)std::min<int64_t>(4096, (arena_len + 255) / 256);

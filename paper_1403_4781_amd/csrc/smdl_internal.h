@@ -146,7 +146,8 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
                       int32_t* fill, int32_t* ptr, int32_t* list_sig, float* list_coef, int32_t* status,
                       int max_kpad, double* arena, double* part, int64_t arena_len, int chunks, int solver,
                       int32_t* bcnt, int32_t* bbase, hipStream_t st);
-// Blocks of the code transpose for sets of at most max_n signals.
+// Blocks of the fixed-order code transpose (per-block counts and bases) for sets of at most max_n
+// signals.
 int64_t mod_csc_blocks(int64_t max_n);
 
 // Misc kernels.

@@ -160,6 +160,42 @@ def test_mod_concentrated_lists(h, dev, deterministic):
     assert err <= D_TOL
 
 
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_mod_repeated_atoms_in_a_code(h, dev, deterministic):
+    """Codes that name one atom in two slots (a fifth of the signals, the second slot a copy of the
+    first atom with its own coefficient): both list modes treat the two slots as two entries, so
+    the products are those of the summed coefficient, as in the oracle's MOD, which adds every
+    pair of slots.  The fixed-order mode repeats bit for bit."""
+    import paper_1403_4781_amd as smdl
+    print(f"case mod repeated atoms deterministic={deterministic}", flush=True)
+    rng = np.random.default_rng(3300)
+    m, K, N, S = 64, 128, 2500, 8
+    Y = rng.standard_normal((N, m)).astype(np.float32)
+    idx = np.stack([rng.choice(K, S, replace=False) for _ in range(N)]).astype(np.int32)
+    rep = np.arange(N) % 5 == 0
+    idx[rep, 3] = idx[rep, 0]
+    coef = rng.standard_normal((N, S)).astype(np.float32).astype(np.float64)
+    nnz = np.full(N, S, np.int32)
+    codes = oracle.Codes(idx, coef, nnz)
+    D = synth.gaussian_dictionary(rng, m, K).astype(np.float32)
+    Dref, nu_ref, _ = oracle.mod_update(Y, codes, D)
+    h.set_flags(smdl.SMDL_DETERMINISTIC if deterministic else 0)
+    outs = []
+    try:
+        for _ in range(2 if deterministic else 1):
+            Dg = _t(D, dev)
+            nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+            outs.append(Dg.cpu().numpy())
+    finally:
+        h.set_flags(0)
+    err = np.linalg.norm(outs[0] - Dref, axis=1).max()
+    print(f"  max atom error {err:.3e} unused {nu}/{nu_ref}", flush=True)
+    assert nu == nu_ref
+    assert err <= D_TOL
+    if deterministic:
+        np.testing.assert_array_equal(outs[0], outs[1])
+
+
 def test_mod_solver_mode_checked(h):
     import paper_1403_4781_amd as smdl
     print("case mod solver mode", flush=True)
