@@ -1182,10 +1182,13 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const ModDesc* __restr
 // and the right-hand sides of a block column are requested together with the product's
 // operands, so that each block column waits on global memory about once.  TW: 4 waves when the
 // launch has many work groups, 8 when it has few (more of the product in flight per group;
-// 16 waves measured slower: 452 against 307 us at K = 1024, m = 256).
+// 16 waves measured slower: 452 against 307 us at K = 1024, m = 256).  The 4-wave form is held
+// to 128 registers, so that four work groups fit per CU instead of two: 531 against 604 us for
+// 100 dictionaries at K = 512, m = 256.  Solving the triangle with four lanes per row of D (DPP
+// broadcasts of each finished entry) measured slower in both forms.
 template <int TW>
-__global__ __launch_bounds__(64 * TW) void tri_solve_rows_kernel(const ModDesc* __restrict__ md, int m,
-                                                                 const int32_t* __restrict__ status) {
+__global__ __launch_bounds__(64 * TW, TW == 4 ? 4 : 2)
+void tri_solve_rows_kernel(const ModDesc* __restrict__ md, int m, const int32_t* __restrict__ status) {
     constexpr int NT = 64 * TW;
     constexpr int NL = (SB * SB + NT - 1) / NT;      // diagonal-block entries per thread
     constexpr int NZ = (16 * SB + NT - 1) / NT;      // right-hand-side entries per thread
