@@ -131,6 +131,23 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
+// group_sum of a value that is zero outside the first 16 lanes of the group (the terms of the
+// w_i of a step: lane g holds one only for g < k <= 15).  For a 64-lane group the first row's
+// sum, read from lane 0, is the group's sum (the other rows add exact zeros) and costs one
+// v_readlane instead of the two cross-row exchanges and adds.
+template <int G>
+__device__ __forceinline__ float group_sum_head(float v) {
+    if constexpr (G == 64) {
+        v += __int_as_float(dpp_i<0xB1>(__float_as_int(v), 0));
+        v += __int_as_float(dpp_i<0x4E>(__float_as_int(v), 0));
+        v += __int_as_float(dpp_i<0x141>(__float_as_int(v), 0));
+        v += __int_as_float(dpp_i<0x140>(__float_as_int(v), 0));
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    } else {
+        return group_sum<G>(v);
+    }
+}
+
 // Whether a tile keeps the directions scaled (u_i) rather than unscaled (v_i = l_i u_i, with the
 // 1 / l_i applied to the k coefficients of each update instead): scaled costs EM multiplies per
 // step and saves the SM registers of the 1 / l_i, which the 16-step tiles need.
@@ -319,11 +336,12 @@ __device__ __forceinline__ bool omp_step(State<EM, SM>& st, const StepCtx& x) {
         const float gjj = gload(x.gram, row + 4u * (uint32_t)j);
         const float a0j = x.arow[j];
         // w = Linv g (= u_i(j), the earlier directions at atom j): w_i = sum_g Linv[i][g] G[j, sel_g]
+        static_assert(SM <= 16, "the w terms lie in the first 16 lanes of a group");
         float w[KK > 0 ? KK : 1];
         float l2 = gjj;
 #pragma unroll
         for (int i = 0; i < KK; ++i) {
-            w[i] = group_sum<G>(st.Lc[i] * gsg);
+            w[i] = group_sum_head<G>(st.Lc[i] * gsg);
             l2 = fmaf(-w[i], w[i], l2);
         }
         // d_j (numerically) in the span of the chosen atoms: the signal stops here.  The update
