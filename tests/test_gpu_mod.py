@@ -196,6 +196,38 @@ def test_mod_repeated_atoms_in_a_code(h, dev, deterministic):
         np.testing.assert_array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_mod_long_lists_split_over_blocks(h, dev, deterministic):
+    """About 1200 entries per atom (K=40, s=6, 8000 signals): each atom's list is split over three
+    blocks whose partial columns are added in a fixed order.  Teacher-forced against the oracle's
+    MOD in both list modes; the fixed-order mode repeats bit for bit."""
+    import paper_1403_4781_amd as smdl
+    print(f"case mod long lists deterministic={deterministic}", flush=True)
+    rng = np.random.default_rng(3400)
+    m, K, S, N = 20, 40, 6, 8000
+    Y = rng.standard_normal((N, m)).astype(np.float32)
+    idx = np.argsort(rng.random((N, K)), axis=1)[:, :S].astype(np.int32)
+    coef = rng.standard_normal((N, S)).astype(np.float32).astype(np.float64)
+    codes = oracle.Codes(idx, coef, np.full(N, S, np.int32))
+    D = synth.gaussian_dictionary(rng, m, K).astype(np.float32)
+    Dref, nu_ref, _ = oracle.mod_update(Y, codes, D)
+    h.set_flags(smdl.SMDL_DETERMINISTIC if deterministic else 0)
+    outs = []
+    try:
+        for _ in range(2 if deterministic else 1):
+            Dg = _t(D, dev)
+            nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+            outs.append(Dg.cpu().numpy())
+    finally:
+        h.set_flags(0)
+    err = np.linalg.norm(outs[0] - Dref, axis=1).max()
+    print(f"  max atom error {err:.3e} unused {nu}/{nu_ref}", flush=True)
+    assert nu == nu_ref == 0
+    assert err <= D_TOL
+    if deterministic:
+        np.testing.assert_array_equal(outs[0], outs[1])
+
+
 def test_mod_solver_mode_checked(h):
     import paper_1403_4781_amd as smdl
     print("case mod solver mode", flush=True)
