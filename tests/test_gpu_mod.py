@@ -228,6 +228,36 @@ def test_mod_long_lists_split_over_blocks(h, dev, deterministic):
         np.testing.assert_array_equal(outs[0], outs[1])
 
 
+def test_mod_fixed_order_largest_dictionary(h, dev):
+    """The fixed-order mode at K=1024 (the largest dictionary: 32 KB of atom masks in the list fill
+    and in the products), m=64, s=16, 20000 random codes: against the oracle's MOD, and bit for bit
+    on a second run."""
+    import paper_1403_4781_amd as smdl
+    print("case mod fixed order K=1024 m=64 s=16 N=20000", flush=True)
+    rng = np.random.default_rng(3500)
+    m, K, S, N = 64, 1024, 16, 20000
+    Y = rng.standard_normal((N, m)).astype(np.float32)
+    idx = np.argsort(rng.random((N, K)), axis=1)[:, :S].astype(np.int32)
+    coef = rng.standard_normal((N, S)).astype(np.float32).astype(np.float64)
+    codes = oracle.Codes(idx, coef, np.full(N, S, np.int32))
+    D = synth.gaussian_dictionary(rng, m, K).astype(np.float32)
+    Dref, nu_ref, _ = oracle.mod_update(Y, codes, D)
+    h.set_flags(smdl.SMDL_DETERMINISTIC)
+    outs = []
+    try:
+        for _ in range(2):
+            Dg = _t(D, dev)
+            nu = h.mod_update(_t(Y, dev), _gpu_codes(codes, dev), Dg)
+            outs.append(Dg.cpu().numpy())
+    finally:
+        h.set_flags(0)
+    err = np.linalg.norm(outs[0] - Dref, axis=1).max()
+    print(f"  max atom error {err:.3e} unused {nu}/{nu_ref}", flush=True)
+    assert nu == nu_ref
+    assert err <= D_TOL
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
 def test_mod_solver_mode_checked(h):
     import paper_1403_4781_amd as smdl
     print("case mod solver mode", flush=True)
