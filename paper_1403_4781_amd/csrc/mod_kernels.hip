@@ -300,7 +300,7 @@ constexpr int MP_LDS = SMDL_MAX_K * 8 + 256 * 8 + MP_STAGE * 8;
 // same column of copy c - 1 of the M arena in `part` (sum_reduce_kernel adds the copies in a
 // fixed order).  Long lists (many signals per atom) are so spread over P blocks.
 // Fixed-order mode (FIXED): the A column is summed in list order without atomics.  Each round
-// takes 16 entries x 16 support slots, one (entry, slot) pair per thread, keyed 16 entry + slot;
+// takes 256 / SP entries x SP support slots, one (entry, slot) pair per thread, keyed SP entry + slot;
 // a pair sets its key's bit in its target atom's 256-bit mask (dynamic LDS, 8 words per atom)
 // and the pair with the lowest key of each target adds the round's values of that target in key
 // order.  B is in list order in both modes.
@@ -350,17 +350,20 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
             }
             __syncthreads();
             // A column: every entry (n, x_na) adds x_na * x_nl at every atom l of signal n; the
-            // block's lanes take (entry, support slot) pairs, 16 entries per round, the loads of
-            // UA rounds issued before their adds (s_stride <= 16 slots per entry)
+            // block's lanes take (entry, support slot) pairs, SP slots per entry (s_stride rounded
+            // up to a power of two, at most 16) and 256 / SP entries per round, the loads of UA
+            // rounds issued before their adds
             constexpr int UA = 4;
-            const int slot = tid & 15, eq = tid >> 4;
-            for (int q0 = 0; q0 < cnt; q0 += 16 * UA) {
+            const int lsp = d.s_stride <= 1 ? 0 : 32 - __clz(d.s_stride - 1);
+            const int SP = 1 << lsp, ER = 256 >> lsp;
+            const int slot = tid & (SP - 1), eq = tid >> lsp;
+            for (int q0 = 0; q0 < cnt; q0 += ER * UA) {
                 int lv[UA], kv[UA];
                 float cv[UA];
                 double xv[UA];
 #pragma unroll
                 for (int u = 0; u < UA; ++u) {
-                    const int q = q0 + 16 * u + eq;
+                    const int q = q0 + ER * u + eq;
                     lv[u] = -1;
                     kv[u] = 0;
                     cv[u] = 0.f;
