@@ -433,9 +433,10 @@ def run_denoise(args, smdl, synth, torch, dev):
 
 def run_modsolve(args, smdl, synth, torch, dev):
     """The MOD update at the shapes of the workloads, with each factorisation of the normal
-    equations forced in turn (2: one work group per dictionary, 1: multi-work-group panels): one
-    JSON line per shape with the wall time of one smdl_mod_update (transpose, products, solve,
-    normalisation; mean of 10 after one warm-up) and the largest difference of the two results."""
+    equations forced in turn (2: one work group per dictionary, 1: multi-work-group panels), then
+    in the fixed-order mode: one JSON line per shape with the wall time of one smdl_mod_update
+    (transpose, products, solve, normalisation; mean of 10 after one warm-up) and the largest
+    differences of the results."""
     h = smdl.Handle(0)
     rng = np.random.default_rng(synth.SEED_BASE + 300)
     shapes = [("merge, patch scale", 64, 256, 4, 5120), ("local, patch scale", 64, 256, 8, 5000),
@@ -447,8 +448,11 @@ def run_modsolve(args, smdl, synth, torch, dev):
         Y = torch.randn(N, m, device=dev)
         D0 = torch.from_numpy(synth.gaussian_dictionary(rng, m, K).astype(np.float32)).to(dev)
         res = {}
-        for solver in (2, 1):
+        # (factorisation, handle flags): each forced factorisation, then the default one in the
+        # fixed-order mode (code lists and product sums in a fixed order)
+        for key, solver, flags in ((2, 2, 0), (1, 1, 0), ("fixed", 0, smdl.SMDL_DETERMINISTIC)):
             h.set_mod_solver(solver)
+            h.set_flags(flags)
             D = D0.clone()
             h.mod_update(Y, X, D)
             torch.cuda.synchronize()
@@ -457,11 +461,15 @@ def run_modsolve(args, smdl, synth, torch, dev):
                 D = D0.clone()
                 h.mod_update(Y, X, D)
             torch.cuda.synchronize()
-            res[solver] = ((time.perf_counter() - t0) / 10 * 1e3, D.cpu().numpy())
+            res[key] = ((time.perf_counter() - t0) / 10 * 1e3, D.cpu().numpy())
         h.set_mod_solver(0)
+        h.set_flags(0)
         print(json.dumps({"shape": name, "m": m, "K": K, "s": s, "N": N,
                           "one_work_group_ms": round(res[2][0], 3), "multi_work_group_ms": round(res[1][0], 3),
-                          "max_abs_difference": float(np.abs(res[1][1] - res[2][1]).max())}), flush=True)
+                          "max_abs_difference": float(np.abs(res[1][1] - res[2][1]).max()),
+                          "fixed_order_ms": round(res["fixed"][0], 3),
+                          "fixed_order_max_abs_difference": float(np.abs(res["fixed"][1] - res[1][1]).max())}),
+              flush=True)
 
 
 def main():
