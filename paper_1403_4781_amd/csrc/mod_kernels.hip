@@ -301,9 +301,9 @@ constexpr int MP_LDS = SMDL_MAX_K * 8 + 256 * 8 + MP_STAGE * 8;
 // fixed order).  Long lists (many signals per atom) are so spread over P blocks.
 // Fixed-order mode (FIXED): the A column is summed in list order without atomics.  Each round
 // takes 256 / SP entries x SP support slots, one (entry, slot) pair per thread, keyed SP entry + slot;
-// a pair sets its key's bit in its target atom's 256-bit mask (dynamic LDS, 8 words per atom)
-// and the pair with the lowest key of each target adds the round's values of that target in key
-// order.  B is in list order in both modes.
+// a pair sets its key's bit in its target atom's 256-bit mask and takes the minimum of its key
+// in the target's owner word (dynamic LDS, 9 words per atom); the owner adds the round's values
+// of that target in key order.  B is in list order in both modes.
 template <bool FIXED>
 __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __restrict__ md, int m,
                                                            const int32_t* __restrict__ ptr,
@@ -322,12 +322,15 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
     __shared__ double partB[256];            // groups x mcov = 256 row sums
     __shared__ int32_t s_sig[PSTAGE];
     __shared__ float s_cf[PSTAGE];
-    extern __shared__ uint32_t amask[];      // fixed-order mode: Kpad x 8 words
+    extern __shared__ uint32_t amask[];      // fixed-order mode: Kpad x 8 mask words, Kpad owners
     __shared__ double vbuf[FIXED ? 256 : 1];
     const int tid = threadIdx.x;
     for (int l = tid; l < d.Kpad; l += 256) colA[l] = 0.0;
-    if constexpr (FIXED)
+    int32_t* owner = reinterpret_cast<int32_t*>(amask + 8 * d.Kpad);   // fixed-order mode: Kpad
+    if constexpr (FIXED) {
         for (int w = tid; w < d.Kpad * 8; w += 256) amask[w] = 0u;
+        for (int l = tid; l < d.Kpad; l += 256) owner[l] = 0x7fffffff;
+    }
     __syncthreads();
     const int64_t ld = d.Kpad + m;
     double* out = (c == 0 ? d.A : part + (int64_t)(c - 1) * arena_len + (d.A - arena)) + (int64_t)a * ld;
@@ -388,27 +391,26 @@ __global__ __launch_bounds__(256) void mod_products_kernel(const ModDesc* __rest
                         if (ok) {
                             vbuf[tid] = xv[u] * (double)cv[u];
                             atomicOr(&amask[lv[u] * 8 + wd], bit);
+                            atomicMin(&owner[lv[u]], tid);
                         }
                         __syncthreads();
-                        bool lead = false;
-                        if (ok) {
-                            const uint32_t* mk = &amask[lv[u] * 8];
-                            lead = (mk[wd] & (bit - 1u)) == 0u;
-                            for (int w = 0; w < wd && lead; ++w) lead = mk[w] == 0u;
-                            if (lead) {
-                                double acc = colA[lv[u]];
-                                for (int w = wd; w < 8; ++w) {
-                                    uint32_t b = mk[w];
-                                    while (b) {
-                                        acc += vbuf[32 * w + __builtin_ctz(b)];
-                                        b &= b - 1u;
-                                    }
+                        // the owner (lowest key) of each target adds its values, then clears the
+                        // target's mask and owner word for the next round; any other pair reads
+                        // the lowest key or the cleared word, neither of which is its own key
+                        if (ok && owner[lv[u]] == tid) {
+                            uint32_t* mk = &amask[lv[u] * 8];
+                            double acc = colA[lv[u]];
+                            for (int w = wd; w < 8; ++w) {
+                                uint32_t b = mk[w];
+                                while (b) {
+                                    acc += vbuf[32 * w + __builtin_ctz(b)];
+                                    b &= b - 1u;
                                 }
-                                colA[lv[u]] = acc;
+                                mk[w] = 0u;
                             }
+                            colA[lv[u]] = acc;
+                            owner[lv[u]] = 0x7fffffff;
                         }
-                        __syncthreads();             // every mask is read
-                        if (ok) amask[lv[u] * 8 + wd] = 0u;
                         __syncthreads();
                     } else {
                         if (ok) atomicAdd(&colA[lv[u]], xv[u] * (double)cv[u]);
@@ -1356,11 +1358,11 @@ hipError_t launch_mod(const ModDesc* dev_desc, int n_desc, int m, int total_atom
     // XCD's 4 MB L2, fewer blocks in flight gather from fewer dictionaries at once: unused dynamic
     // LDS caps the launch at 6 blocks per CU (at m=256 and 10^4 signals per dictionary 5 % faster
     // than 8 blocks; 3, 4 and 5 blocks are slower than 6).  The fixed-order mode's masks take
-    // 32 bytes per atom of dynamic LDS.
+    // 36 bytes per atom of dynamic LDS.
     static_assert(8 * MP_LDS <= 160 * 1024, "8 blocks of mod_products_kernel per CU");
     if (fixed) {
         hipLaunchKernelGGL(mod_products_kernel<true>, dim3(max_kpad, n_desc, chunks), dim3(256),
-                           (unsigned)max_kpad * 32u, st, dev_desc, m, ptr, list_sig, list_coef, arena, part, arena_len);
+                           (unsigned)max_kpad * 36u, st, dev_desc, m, ptr, list_sig, list_coef, arena, part, arena_len);
     } else {
         const bool mp_cap = (int64_t)max_n * m * 4 > ((int64_t)4 << 20);
         const unsigned mp_pad = mp_cap ? (unsigned)(160 * 1024 / 6 - 1024 - MP_LDS) : 0u;
